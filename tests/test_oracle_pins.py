@@ -1,0 +1,466 @@
+"""Pins of the FP64 oracle against closed forms, invariants, library routines and brute force.
+
+Each test checks the oracle against something other than itself, so that a plausible
+mistake in it (a dropped term, a wrong sign or index, a transposed operand) fails.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+from scipy.interpolate import RegularGridInterpolator
+from scipy.sparse.csgraph import shortest_path
+from scipy.spatial.transform import Rotation
+
+import oracle
+from paper_2304_09953_amd import inputs as I
+
+RNG = np.random.default_rng(12345)
+
+
+def small_pocket(dims=(7, 6, 5), n_types=2, origin=(-1.0, -0.5, 0.25), spacing=0.5, **kw):
+    R, e, q = I.type_table(n_types)
+    return I.Pocket(tuple(dims), n_types, np.asarray(origin, np.float32), spacing, np.zeros((1, 3), np.float32),
+                    np.zeros(1, np.int32), R, e, q, **kw)
+
+
+# ------------------------------------------------------------------------------------------------
+# Rotations
+# ------------------------------------------------------------------------------------------------
+
+def test_quat_matrix_matches_scipy_and_is_proper():
+    for _ in range(50):
+        q = RNG.normal(size=4) * RNG.uniform(0.2, 3.0)  # unnormalised on purpose
+        R = oracle.quat_matrix(q)
+        ref = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()  # scipy is scalar-last
+        assert np.allclose(R, ref, atol=1e-14)
+        assert np.allclose(R @ R.T, np.eye(3), atol=1e-14)
+        assert abs(np.linalg.det(R) - 1.0) < 1e-14
+    assert np.allclose(oracle.quat_matrix([1, 0, 0, 0]), np.eye(3), atol=0)
+    # active right-hand rotation: 90 degrees about z takes x to y
+    c = math.cos(math.pi / 4)
+    assert np.allclose(oracle.quat_matrix([c, 0, 0, c]) @ [1, 0, 0], [0, 1, 0], atol=1e-15)
+
+
+def test_rodrigues_matches_quaternion_and_scipy():
+    for _ in range(50):
+        u = RNG.normal(size=3)
+        u /= np.linalg.norm(u)
+        th = RNG.uniform(-7, 7)
+        v = RNG.normal(size=3) * 3
+        r = oracle.rodrigues(u, th, v)
+        assert np.allclose(r, Rotation.from_rotvec(th * u).apply(v), atol=1e-13)
+        # the quaternion (cos th/2, sin th/2 u) is the same rotation
+        q = np.r_[math.cos(th / 2), math.sin(th / 2) * u]
+        assert np.allclose(r, oracle.quat_matrix(q) @ v, atol=1e-13)
+
+
+def test_rodrigues_S_steps_is_identity():
+    u = np.array([1.0, 2.0, -2.0]) / 3.0
+    v0 = np.array([0.3, -1.2, 2.5])
+    for S in (8, 64, 256):
+        v = v0.copy()
+        for _ in range(S):
+            v = oracle.rodrigues(u, 2 * math.pi / S, v)
+        assert np.allclose(v, v0, atol=1e-12)
+
+
+# ------------------------------------------------------------------------------------------------
+# Pair potential and grids
+# ------------------------------------------------------------------------------------------------
+
+def test_pair_potential_lj_minimum_and_floor():
+    p = small_pocket(n_types=3)
+    p.type_q = np.zeros(3)  # pure Lennard-Jones-like well
+    for a, b in [(0, 0), (1, 2), (2, 0)]:
+        r0 = p.type_R[a] + p.type_R[b]
+        eps = math.sqrt(p.type_eps[a] * p.type_eps[b])
+        assert oracle.pair_energy(p, r0, a, b) == pytest.approx(-eps, rel=1e-13)
+        h = 1e-5
+        d = (oracle.pair_energy(p, r0 + h, a, b) - oracle.pair_energy(p, r0 - h, a, b)) / (2 * h)
+        assert abs(d) < 1e-6  # minimum of the well at r0
+        assert oracle.pair_energy(p, 0.8 * r0, a, b) > 0 > oracle.pair_energy(p, 1.5 * r0, a, b)
+        assert oracle.pair_energy(p, 0.1, a, b) == oracle.pair_energy(p, p.r_min, a, b)
+
+
+def test_pair_potential_coulomb_tail():
+    p = small_pocket(n_types=4)
+    p.type_eps = np.zeros(4)  # pure Coulomb-like term
+    for a, b in [(0, 3), (1, 1), (2, 0)]:
+        for r in (1.0, 5.0, 40.0):
+            ref = 332.0636 / 4.0 * p.type_q[a] * p.type_q[b] / r
+            assert oracle.pair_energy(p, r, a, b) == pytest.approx(ref, rel=1e-13, abs=1e-15)
+
+
+def _pocket_with_atoms(xyz, types, dims=(9, 9, 9), spacing=0.5, origin=(0.0, 0.0, 0.0), cap=10.0):
+    p = small_pocket(dims=dims, n_types=2, origin=origin, spacing=spacing, cap=cap)
+    p.prot_xyz = np.asarray(xyz, np.float32).reshape(-1, 3)
+    p.prot_type = np.asarray(types, np.int32)
+    return p
+
+
+def test_grid_layout_and_symmetry_single_atom():
+    # one protein atom exactly on node (4, 4, 4): values depend only on the node distance
+    p = _pocket_with_atoms([[2.0, 2.0, 2.0]], [1])
+    G = oracle.build_grids(p)  # [t][z][y][x]
+    for t in range(2):
+        g = G[t]
+        assert g[4, 4, 4] == 10.0  # capped on top of the atom
+        for d in (1, 2, 3):
+            vals = [g[4, 4, 4 + d], g[4, 4, 4 - d], g[4, 4 + d, 4], g[4, 4 - d, 4], g[4 + d, 4, 4], g[4 - d, 4, 4]]
+            assert np.all(np.array(vals) == vals[0])
+        assert np.array_equal(g, np.transpose(g, (2, 1, 0)))
+    # grid value at a node equals the capped pair energy at that node's distance
+    r = math.sqrt(3 ** 2 + 1 ** 2) * 0.5
+    assert G[0, 4, 4 + 1, 4 + 3] == np.float32(min(10.0, oracle.pair_energy(p, r, 0, 1)))
+
+
+def test_grid_superposition_and_cap():
+    xyz = RNG.uniform(-1, 5, size=(6, 3))
+    typ = RNG.integers(0, 2, size=6)
+    big = 1e30
+    pa = _pocket_with_atoms(xyz[:3], typ[:3], dims=(6, 5, 4), cap=big)
+    pb = _pocket_with_atoms(xyz[3:], typ[3:], dims=(6, 5, 4), cap=big)
+    pab = _pocket_with_atoms(xyz, typ, dims=(6, 5, 4), cap=big)
+    _, ga = oracle.build_grids(pa, want64=True)
+    _, gb = oracle.build_grids(pb, want64=True)
+    _, gab = oracle.build_grids(pab, want64=True)
+    assert np.allclose(gab, ga + gb, rtol=1e-12, atol=1e-12)
+    capped = _pocket_with_atoms(xyz, typ, dims=(6, 5, 4), cap=10.0)
+    _, gc = oracle.build_grids(capped, want64=True)
+    assert np.array_equal(gc, np.minimum(gab, 10.0))
+    # sampled-node entry point agrees with the full build
+    tijk = np.array([[1, 2, 3, 1], [0, 5, 4, 3], [1, 0, 0, 0]], np.int32)
+    v = oracle.grid_nodes(capped, tijk)
+    assert np.array_equal(v, [gc[t, k, j, i] for t, i, j, k in tijk])
+
+
+# ------------------------------------------------------------------------------------------------
+# Trilinear interpolation and boundaries
+# ------------------------------------------------------------------------------------------------
+
+def _inside_points(p, n):
+    nx, ny, nz = p.dims
+    u = RNG.uniform(0, 1, size=(n, 3)) * (np.array([nx, ny, nz]) - 1)
+    return p.origin.astype(np.float64) + p.spacing * u, u
+
+
+def test_trilinear_exact_at_nodes():
+    p = small_pocket()
+    G = RNG.normal(size=(2, 5, 6, 7)).astype(np.float32)
+    for _ in range(40):
+        t, i, j, k = RNG.integers(0, 2), RNG.integers(0, 7), RNG.integers(0, 6), RNG.integers(0, 5)
+        x = p.origin + p.spacing * np.array([i, j, k])
+        assert oracle.lookup_points(p, G, [t], [x])[0] == float(G[t, k, j, i])
+
+
+def test_trilinear_exact_on_linear_and_multilinear_fields():
+    p = small_pocket()
+    nz, ny, nx = 5, 6, 7
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    lin = 3.0 - 2.0 * ii + 0.5 * jj + 1.25 * kk
+    mul = ii * jj * kk - 2.0 * ii * jj + 0.75 * kk
+    G = np.stack([lin, mul]).astype(np.float32)
+    x, u = _inside_points(p, 200)
+    got0 = oracle.lookup_points(p, G, np.zeros(200), x)
+    got1 = oracle.lookup_points(p, G, np.ones(200), x)
+    assert np.allclose(got0, 3.0 - 2.0 * u[:, 0] + 0.5 * u[:, 1] + 1.25 * u[:, 2], atol=1e-12)
+    assert np.allclose(got1, u[:, 0] * u[:, 1] * u[:, 2] - 2.0 * u[:, 0] * u[:, 1] + 0.75 * u[:, 2], atol=1e-12)
+
+
+def test_trilinear_matches_scipy_regular_grid_interpolator():
+    p = small_pocket()
+    G = RNG.normal(size=(2, 5, 6, 7)).astype(np.float32)
+    ax = [p.origin[d] + p.spacing * np.arange(n) for d, n in enumerate(p.dims)]
+    x, _ = _inside_points(p, 500)
+    for t in range(2):
+        f = RegularGridInterpolator(ax, np.transpose(G[t].astype(np.float64), (2, 1, 0)), method="linear")
+        assert np.allclose(oracle.lookup_points(p, G, np.full(500, t), x), f(x), atol=1e-12)
+
+
+def test_clamp_restraint_and_continuity():
+    p = small_pocket()
+    G = RNG.normal(size=(2, 5, 6, 7)).astype(np.float32)
+    lo = p.origin.astype(np.float64)
+    hi = lo + p.spacing * (np.array(p.dims) - 1)
+    for _ in range(50):
+        x = RNG.uniform(lo - 3, hi + 3)
+        xc = np.clip(x, lo, hi)
+        v = oracle.lookup_points(p, G, [1], [x])[0]
+        vc = oracle.lookup_points(p, G, [1], [xc])[0]
+        assert v == pytest.approx(vc + p.w_out * np.sum((x - xc) ** 2), abs=1e-12)
+    # continuous through the upper face and through interior cell faces
+    for d in range(3):
+        for face in (hi[d], lo[d] + p.spacing * 2):
+            a = 0.5 * (lo + hi)
+            b = a.copy()
+            a[d] = face - 1e-10
+            b[d] = face + 1e-10
+            va, vb = oracle.lookup_points(p, G, [0, 0], [a, b])
+            assert abs(va - vb) < 1e-8
+
+
+def test_periodic_translation_covariance():
+    p = small_pocket()
+    G = RNG.normal(size=(2, 5, 6, 7)).astype(np.float32)
+    n = np.array(p.dims)
+    x, _ = _inside_points(p, 100)
+    x = x + RNG.uniform(-20, 20, size=(100, 3))  # anywhere
+    t = RNG.integers(0, 2, size=100)
+    base = oracle.lookup_points(p, G, t, x, periodic=True)
+    for d, axis in zip(range(3), (3, 2, 1)):
+        for k in (1, 3, -2):
+            shift = np.zeros(3)
+            shift[d] = p.spacing * k
+            rolled = np.ascontiguousarray(np.roll(G, -k, axis=axis))
+            assert np.allclose(oracle.lookup_points(p, G, t, x + shift, periodic=True),
+                               oracle.lookup_points(p, rolled, t, x, periodic=True), atol=1e-9)
+        full = np.zeros(3)
+        full[d] = p.spacing * n[d]
+        assert np.allclose(oracle.lookup_points(p, G, t, x + full, periodic=True), base, atol=1e-9)
+
+
+# ------------------------------------------------------------------------------------------------
+# Topology
+# ------------------------------------------------------------------------------------------------
+
+def chain(n, rot_bonds, n_types=2, spacing=1.5):
+    xyz = np.zeros((n, 3))
+    for i in range(n):  # zig-zag chain in the xy plane, 120 degree bond angles
+        xyz[i] = [i * spacing * math.cos(math.pi / 6), (i % 2) * spacing * 0.5, 0.0]
+    bonds = [(i, i + 1) for i in range(n - 1)]
+    rot = [1 if b in rot_bonds else 0 for b in bonds]
+    return xyz, np.zeros(n, np.uint8), bonds, rot
+
+
+def test_topology_chain_orientation_core_and_order():
+    ligs = I.from_parts([chain(6, [(2, 3)]), chain(8, [(2, 3), (4, 5)]), chain(7, [(1, 2), (4, 5)])], 2)
+    t0 = oracle.topology(ligs, 0)
+    assert t0["status"] == 0 and t0["B"] == 1
+    assert list(np.flatnonzero(t0["core"])) == [0, 1, 2]  # equal fragments: the one with atom 0
+    assert (t0["tor_a"][0], t0["tor_b"][0]) == (2, 3)
+    assert list(np.flatnonzero(t0["moving"][0])) == [3, 4, 5]
+    t1 = oracle.topology(ligs, 1)
+    assert list(np.flatnonzero(t1["core"])) == [0, 1, 2]
+    assert [list(np.flatnonzero(m)) for m in t1["moving"]] == [[3, 4, 5, 6, 7], [5, 6, 7]]
+    assert list(t1["tor_bond"]) == [2, 4]
+    t2 = oracle.topology(ligs, 2)  # core {2, 3, 4} in the middle: both ends move, equal sizes
+    assert list(np.flatnonzero(t2["core"])) == [2, 3, 4]
+    assert [(a, b) for a, b in zip(t2["tor_a"], t2["tor_b"])] == [(2, 1), (4, 5)]
+    assert [list(np.flatnonzero(m)) for m in t2["moving"]] == [[0, 1], [5, 6]]
+
+
+def test_topology_relabelled_moving_sets_are_descendants():
+    ligs = I.make_ligands(40, I.DIST_CONFIG2, 16, stream="test")
+    for l in range(40):
+        t = oracle.topology(ligs, l)
+        _, _, bonds, rot = ligs.ligand(l)
+        n = len(t["core"])
+        assert t["status"] == 0 and t["B"] == int(rot.sum())
+        sizes = t["moving"].sum(1)
+        assert np.all(np.diff(sizes) <= 0)  # sweep order: larger moving sets first
+        for k in range(t["B"]):
+            m = t["moving"][k]
+            assert not np.any(m & t["core"]) and m[t["tor_b"][k]] and not m[t["tor_a"][k]]
+            for j in range(k):  # nested or disjoint, never crossing
+                mj = t["moving"][j]
+                assert not np.any(m & mj) or np.all(m <= mj)
+        assert t["core"].sum() == max(np.bincount(_fragments(n, bonds, rot)))
+
+
+def _fragments(n, bonds, rot):
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    keep = [b for b, r in zip(bonds, rot) if not r]
+    if not keep:
+        return np.arange(n)
+    keep = np.array(keep)
+    A = coo_matrix((np.ones(len(keep)), (keep[:, 0], keep[:, 1])), shape=(n, n))
+    return connected_components(A, directed=False)[1]
+
+
+def test_clash_pairs_match_shortest_paths():
+    ligs = I.make_ligands(30, I.DIST_CONFIG3, 16, stream="test")
+    for l in range(30):
+        t = oracle.topology(ligs, l)
+        _, _, bonds, _ = ligs.ligand(l)
+        n = len(t["core"])
+        A = np.zeros((n, n))
+        A[bonds[:, 0], bonds[:, 1]] = 1
+        D = shortest_path(A, directed=False, unweighted=True)
+        ii, jj = np.triu_indices(n, 1)
+        ref = set(zip(ii[D[ii, jj] >= 3], jj[D[ii, jj] >= 3]))
+        assert set(map(tuple, t["pairs"])) == ref
+
+
+def _status_of(parts, n_types=2):
+    return oracle.status(I.from_parts(parts, n_types))
+
+
+def test_status_codes_and_their_order():
+    ok = chain(5, [(1, 2)])
+    bad = []
+    x, t, b, r = chain(129, [])
+    bad.append(((x, t, b, r), 1))
+    x, t, b, r = chain(5, [])
+    bad.append(((x, np.array([0, 0, 5, 0, 0], np.uint8), b, r), 2))
+    bad.append(((x, t, b[:3], r[:3]), 3))
+    bad.append(((x, np.array([0, 0, 9, 0, 0], np.uint8), b[:3], r[:3]), 2))  # type checked before bonds
+    bad.append(((x, t, [(0, 1), (1, 2), (2, 3), (3, 7)], r), 4))
+    bad.append(((x, t, [(0, 1), (1, 1), (2, 3), (3, 4)], r), 4))
+    xs = np.zeros((6, 3))
+    bad.append(((xs, np.zeros(6, np.uint8), [(0, 1), (0, 2), (0, 3), (0, 4), (0, 5)], [0] * 5), 5))
+    bad.append(((x, t, [(0, 1), (1, 2), (0, 1), (3, 4)], r), 6))
+    bad.append(((x, t, b, [1, 0, 0, 0]), 7))
+    x, t, b, r = chain(20, [])
+    bad.append(((x, t, b, [0] + [1] * 17 + [0]), 8))
+    x, t, b, r = chain(20, [])
+    parts = [ok] + [p for p, _ in bad]
+    st = _status_of(parts)
+    assert st[0] == 0
+    assert list(st[1:]) == [c for _, c in bad]
+
+
+# ------------------------------------------------------------------------------------------------
+# Motions and score
+# ------------------------------------------------------------------------------------------------
+
+def _dist(X):
+    return np.linalg.norm(X[:, None, :] - X[None, :, :], axis=-1)
+
+
+def test_rigid_start_preserves_shape_and_centres_on_translation(cfg1, cfg1_ligs):
+    s = cfg1.search
+    for l in (0, 7):
+        xyz = cfg1_ligs.ligand(l)[0].astype(np.float64)
+        for p in (0, 5, 300, 511):
+            X = oracle.pose_coords(cfg1_ligs, s, l, p, upto=0)
+            assert np.allclose(_dist(X), _dist(xyz), atol=1e-12)
+            assert np.allclose(X.mean(0), s.trans[p % len(s.trans)], atol=1e-12)
+
+
+def test_torsion_move_invariants():
+    ligs = I.make_ligands(20, I.DIST_CONFIG2, 16, stream="test")
+    srch = I.make_search(4, 2, 16, 2.0, [0, 0, 0])
+    for l in range(20):
+        t = oracle.topology(ligs, l)
+        if t["B"] == 0:
+            continue
+        X0 = oracle.pose_coords(ligs, srch, l, 3, upto=0)
+        bonds = ligs.ligand(l)[2]
+        for k in range(t["B"]):
+            steps = np.zeros(16, np.int32)
+            steps[k] = RNG.integers(1, 16)
+            X1 = oracle.pose_coords(ligs, srch, l, 3, steps)
+            m = t["moving"][k]
+            D0, D1 = _dist(X0), _dist(X1)
+            bl0 = np.linalg.norm(X0[bonds[:, 0]] - X0[bonds[:, 1]], axis=1)
+            bl1 = np.linalg.norm(X1[bonds[:, 0]] - X1[bonds[:, 1]], axis=1)
+            assert np.allclose(bl0, bl1, atol=1e-12)
+            assert np.allclose(D0[np.ix_(m, m)], D1[np.ix_(m, m)], atol=1e-12)
+            assert np.allclose(D0[np.ix_(~m, ~m)], D1[np.ix_(~m, ~m)], atol=1e-12)
+            for end in (t["tor_a"][k], t["tor_b"][k]):
+                assert np.allclose(D0[end], D1[end], atol=1e-12)
+            assert np.allclose(X0[~m], X1[~m], atol=1e-13)
+            if steps[k] != 0:
+                assert not np.allclose(X0[m], X1[m])
+        # all steps of one torsion = a full turn
+        X = oracle.pose_coords(ligs, srch, l, 3, [0] * 16)
+        assert np.allclose(X, X0)
+
+
+def test_score_is_lookups_plus_clash(cfg1, cfg1_grid, cfg1_ligs):
+    p, s = cfg1.pockets[0], cfg1.search
+    for l in range(5):
+        t = oracle.topology(cfg1_ligs, l)
+        types = cfg1_ligs.ligand(l)[1]
+        X = oracle.pose_coords(cfg1_ligs, s, l, 17 * l, RNG.integers(0, 64, size=4))
+        X = X + RNG.normal(scale=0.3, size=X.shape)  # also unphysical geometry with clashes
+        d = np.linalg.norm(X[t["pairs"][:, 0]] - X[t["pairs"][:, 1]], axis=1)
+        ref = oracle.lookup_points(p, cfg1_grid, types, X).sum() + 10.0 * np.sum(np.maximum(0, 2.5 - d) ** 2)
+        assert oracle.score_conformer(p, cfg1_grid, cfg1_ligs, s, l, X) == pytest.approx(ref, rel=1e-12)
+
+
+def test_clash_closed_form_and_rigid_invariance():
+    # 4-atom chain: the only clash pair is (0, 3); a zero grid isolates the clash term
+    p = small_pocket(dims=(40, 40, 40), origin=(-10, -10, -10), spacing=0.5)
+    G = np.zeros((2, 40, 40, 40), np.float32)
+    srch = I.make_search(1, 1, 8, 0.0, [0, 0, 0])
+    for d03 in (1.0, 2.0, 2.49, 3.0):
+        # atoms 0 and 3 at distance d03; (0, 3) is the only pair three bonds apart
+        X = np.array([[0, 0, 0], [0.0, 1.5, 0], [1.5, 1.5, 0], [d03, 0.0, 0]], float)
+        ligs = I.from_parts([(X, np.zeros(4, np.uint8), [(0, 1), (1, 2), (2, 3)], [0, 0, 0])], 2)
+        e = oracle.score_conformer(p, G, ligs, srch, 0, X)
+        assert e == pytest.approx(10.0 * max(0.0, 2.5 - d03) ** 2, abs=1e-12)
+        R = Rotation.from_rotvec([0.3, -1.1, 0.7]).as_matrix()
+        e2 = oracle.score_conformer(p, G, ligs, srch, 0, X @ R.T + [1.0, -2.0, 0.5])
+        assert e2 == pytest.approx(e, abs=1e-12)
+
+
+# ------------------------------------------------------------------------------------------------
+# Search against brute force
+# ------------------------------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def tiny():
+    p = I.make_pocket(32, 4, pocket_id=9)
+    G = oracle.build_grids(p)
+    ligs = I.make_ligands(60, I.DIST_TINY, 4, stream="tiny")
+    srch = I.make_search(8, 2, 8, 2.0, p.center)
+    return p, G, ligs, srch
+
+
+def test_greedy_equals_exhaustive_for_B0_B1_and_bounds_it_otherwise(tiny):
+    p, G, ligs, srch = tiny
+    nrot = ligs.n_rot
+    res = oracle.dock(p, G, ligs, srch)
+    seen = set()
+    for l in range(ligs.n_lig):
+        ex, exp_, exs = oracle.exhaustive(p, G, ligs, srch, l)
+        B = int(nrot[l])
+        seen.add(B)
+        if B <= 1:
+            assert res["best"][l] == ex
+            assert res["start"][l] == exp_ and np.array_equal(res["steps"][l][:B], exs[:B])
+        else:
+            assert res["best"][l] >= ex - 1e-12
+    assert {0, 1, 2}.issubset(seen)
+
+
+def test_greedy_equals_exhaustive_for_separable_arms():
+    # zig-zag chain of 12 atoms, two end arms far apart: the score separates over the two torsions
+    xyz, t, b, r = chain(12, [(1, 2), (9, 10)])
+    ligs = I.from_parts([(xyz, np.array([0, 1, 2, 3] * 3, np.uint8), b, r)], 4)
+    p = I.make_pocket(48, 4, pocket_id=3)
+    G = oracle.build_grids(p)
+    srch = I.make_search(6, 2, 16, 1.0, p.center)
+    res = oracle.dock(p, G, ligs, srch)
+    ex, _, _ = oracle.exhaustive(p, G, ligs, srch, 0)
+    assert res["best"][0] == pytest.approx(ex, abs=1e-10)
+
+
+# ------------------------------------------------------------------------------------------------
+# Ranking and counting
+# ------------------------------------------------------------------------------------------------
+
+def test_topk_against_python_sort_with_ties():
+    s = RNG.integers(0, 6, size=300).astype(np.float64)
+    s[RNG.integers(0, 300, size=10)] = np.inf
+    ids = RNG.permutation(300) + 1000
+    for k in (1, 7, 100, 300):
+        got_s, got_i = oracle.topk(s, k, ids)
+        ref = sorted(zip(s.tolist(), ids.tolist()))[:k]
+        assert list(zip(got_s.tolist(), got_i.tolist())) == ref
+
+
+def test_pose_count_by_enumeration():
+    n_rot = np.array([0, 1, 3, 2])
+    st = np.array([0, 0, 0, 6])
+    Q, T, S = 3, 2, 5
+    count = 0
+    for l in range(4):
+        if st[l]:
+            continue
+        for _ in range(Q * T):
+            count += 1 + sum(S - 1 for _ in range(n_rot[l]))  # the incumbent is not rescored per sweep
+    assert oracle.pose_count(n_rot, st, Q * T, S) == count
