@@ -1,0 +1,185 @@
+/*
+ * ligate_dock.h - C ABI of the MI355X docking screen.
+ *
+ * The operation (paper §2, "LIGATE CADD Workflow"): rank a virtual ligand
+ * library against one rigid binding site.  A receptor is prepared once as
+ * per-atom-type interaction grids; ligands stream through a pose search with
+ * multiple restarts scored by a geometric function; a ligand's score is the
+ * score of its best pose; the library is ranked and the strongest binders are
+ * returned.  Batching of ligands of uneven size follows §3.3 ("LiGen
+ * Autotuning", the batch redesign).
+ *
+ * Conventions shared by every call:
+ *  - Pointers named d_* are device (HIP) memory, h_* are host memory.  The
+ *    caller owns every buffer; the library never allocates device memory.
+ *    Scratch comes in through d_ws, sized by a query: pass d_ws == NULL and the
+ *    required size is written to *ws_bytes (nothing is enqueued).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *    enqueues work on it: no device allocation, no host synchronisation, no
+ *    hipMemset, so every call can be captured into a hipGraph.
+ *  - Argument errors are returned synchronously (negative status) before any
+ *    work is enqueued.  Data-dependent problems with a ligand (a bond graph that
+ *    is not a tree, ...) are not call failures: they are reported per ligand in
+ *    d_status and such a ligand scores +inf.
+ *  - A HIP launch failure returns DOCK_ERR_HIP; dock_last_error() has detail.
+ *  - Calls are not thread-safe on one stream; different streams are independent.
+ */
+#ifndef LIGATE_DOCK_H
+#define LIGATE_DOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- call status ------------------------------------------------------------------------- */
+#define DOCK_OK 0
+#define DOCK_ERR_INVALID_ARG (-1) /* null pointer, bad count or size, inconsistent descriptor */
+#define DOCK_ERR_LIMIT (-2)       /* a documented limit below is exceeded */
+#define DOCK_ERR_HIP (-3)         /* the HIP runtime reported an error */
+#define DOCK_ERR_WORKSPACE (-4)   /* d_ws / d_pack smaller than the queried size */
+
+/* ---- per-ligand status (d_status), checked in this order; the first failure is reported ---- */
+#define DOCK_LIG_OK 0
+#define DOCK_LIG_NATOMS 1       /* n < 1 or n > DOCK_MAX_ATOMS */
+#define DOCK_LIG_TYPE 2         /* an atom type >= n_types */
+#define DOCK_LIG_NBONDS 3       /* bond count != n - 1 */
+#define DOCK_LIG_BOND_INDEX 4   /* bond endpoint outside [0, n) or a self bond */
+#define DOCK_LIG_DEGREE 5       /* an atom with more than 4 bonds */
+#define DOCK_LIG_NOT_TREE 6     /* the bond graph is not connected */
+#define DOCK_LIG_TERMINAL_ROT 7 /* a rotatable bond with an endpoint of degree 1 */
+#define DOCK_LIG_NTORSIONS 8    /* more than DOCK_MAX_TORSIONS rotatable bonds */
+
+/* ---- limits ------------------------------------------------------------------------------- */
+#define DOCK_MAX_ATOMS 128
+#define DOCK_MAX_TORSIONS 16
+#define DOCK_MAX_TYPES 32
+#define DOCK_MAX_STEPS 1024
+
+#define DOCK_LAYOUT_LINEAR 0     /* grids [t][z][y][x], FP32, x fastest */
+#define DOCK_BOUNDARY_CLAMP 0    /* clamp into the box + w_out * |x - clamp(x)|^2 */
+#define DOCK_BOUNDARY_PERIODIC 1 /* indices wrap modulo the grid size */
+
+/*
+ * Receptor grid frame.  Node (i, j, k) sits at origin + spacing * (i, j, k);
+ * 2 <= nx, ny, nz; nx*ny*nz < 2^24; 1 <= n_types <= DOCK_MAX_TYPES; spacing > 0.
+ */
+typedef struct {
+    int32_t nx, ny, nz, n_types;
+    float origin[3];
+    float spacing;  /* Angstrom */
+    int32_t layout; /* DOCK_LAYOUT_LINEAR */
+    int32_t boundary;
+    float w_out;    /* restraint weight for DOCK_BOUNDARY_CLAMP */
+} dock_grid_desc;
+
+/* Per atom type: radius R (Angstrom), well depth eps, partial charge q. */
+typedef struct {
+    double R, eps, q;
+} dock_type_param;
+
+/* Grid potential: values are capped at `cap`; distances floored at r_min; Coulomb constant / dielectric. */
+typedef struct {
+    double cap, r_min, coulomb_k;
+} dock_potential;
+
+/*
+ * Pose search.  Rigid start p = iq * n_trans + it places the centred ligand
+ * with quaternion d_quat[iq] (w, x, y, z; normalised by the library) and
+ * translation d_trans[it]; then one greedy pass turns each torsion, in sweep
+ * order, by the best of the n_steps angles 2 pi s / n_steps.
+ */
+typedef struct {
+    int32_t n_quat;
+    const float *d_quat;  /* [n_quat][4], device */
+    int32_t n_trans;
+    const float *d_trans; /* [n_trans][3], device, Angstrom */
+    int32_t n_steps;      /* 1 .. DOCK_MAX_STEPS */
+    float clash_cut;      /* pairs three or more bonds apart closer than this clash */
+    float clash_w;        /* clash weight: clash_w * (clash_cut - d)^2 */
+    int32_t starts_per_item; /* rigid starts per work item; 0 = chosen by the library */
+    int32_t waves_per_block; /* 1, 2, 4 or 8; 0 = chosen by the library */
+} dock_search;
+
+/* Size in bytes of the grids for descriptor g. */
+int dock_grid_bytes(const dock_grid_desc *g, size_t *bytes);
+
+/*
+ * Builds the receptor grids: for every ligand atom type t and node x,
+ * G_t(x) = min(cap, sum_j E(t, type_j, |x - p_j|)) with
+ * E(a, b, r) = sqrt(eps_a eps_b) [(r0/r')^12 - 2 (r0/r')^6] + coulomb_k q_a q_b / r',
+ * r0 = R_a + R_b, r' = max(r, r_min); summed in FP64, stored in FP32.
+ * d_prot_xyz: [n_prot][3] FP32; d_prot_type: [n_prot] in [0, n_types);
+ * h_params: [n_types] host; d_grids: dock_grid_bytes(g) bytes.
+ */
+int dock_build_grids(const dock_grid_desc *g, const float *d_prot_xyz, const int32_t *d_prot_type, int32_t n_prot,
+                     const dock_type_param *h_params, const dock_potential *pot, float *d_grids, void *stream);
+
+/*
+ * Packs a ligand library for the screen: centres each input conformer on its
+ * unweighted centroid, stores coordinates as SoA, validates the bond tree,
+ * finds the core (largest rigid fragment; ties to the one holding the lowest
+ * atom index), orients each rotatable bond away from the core with a 128-bit
+ * moving-atom mask, orders torsions for the sweep (larger moving sets first,
+ * ties by bond index) and records, per atom, the atoms fewer than three bonds
+ * away (excluded from the clash term).
+ * Input (device, CSR): d_atom_off [n_lig+1], d_xyz [n_atoms_total][3] FP32,
+ * d_type [n_atoms_total], d_bond_off [n_lig+1], d_bonds [n_bonds][2] (local
+ * atom indices), d_rot [n_bonds] (nonzero = rotatable).  n_atoms_total must be
+ * d_atom_off[n_lig].  With d_pack == NULL the required size is written to
+ * *pack_bytes; otherwise *pack_bytes is the size of d_pack.  d_status [n_lig]
+ * receives DOCK_LIG_* codes.  The pack is opaque and device-resident.
+ */
+int dock_pack_ligands(const int32_t *d_atom_off, const float *d_xyz, const uint8_t *d_type,
+                      const int32_t *d_bond_off, const int32_t *d_bonds, const uint8_t *d_rot, int32_t n_lig,
+                      int64_t n_atoms_total, int32_t n_types, void *d_pack, size_t *pack_bytes, int32_t *d_status,
+                      void *stream);
+
+/*
+ * Docks every packed ligand: all rigid starts, each followed by one greedy
+ * torsion pass; per ligand the lowest final score wins, ties to the lowest
+ * start.  Outputs, indexed by the ligand's position in the packed library:
+ * d_best_score [n_lig] (+inf for a ligand whose status is not OK),
+ * d_best_start [n_lig] (-1 if not OK), d_best_steps [n_lig][16] (the chosen
+ * step of each torsion in sweep order, unused entries 0), optional
+ * d_start_scores [n_lig][n_quat*n_trans] (final score of every start; NULL to
+ * skip), optional d_pose_count [1] (distinct poses scored: per docked ligand
+ * n_quat*n_trans*(1 + B*(n_steps-1))).  n_lig and n_atoms_total must match the
+ * pack.  Workspace: query with d_ws == NULL.
+ */
+int dock_screen(const dock_grid_desc *g, const float *d_grids, const void *d_pack, int32_t n_lig,
+                int64_t n_atoms_total, const dock_search *s, float *d_best_score, int32_t *d_best_start,
+                uint16_t *d_best_steps, float *d_start_scores, uint64_t *d_pose_count, void *d_ws,
+                size_t *ws_bytes, void *stream);
+
+/*
+ * Ranks scores: the k lowest, ties to the lower id, NaN ranked as +inf;
+ * results in ascending order.  d_ids [n] (>= 0) or NULL for ids 0..n-1.
+ * 1 <= k <= n < 2^31.  Workspace: query with d_ws == NULL.
+ */
+int dock_topk(const float *d_scores, const int32_t *d_ids, int64_t n, int32_t k, float *d_out_scores,
+              int32_t *d_out_ids, void *d_ws, size_t *ws_bytes, void *stream);
+
+/*
+ * Scores explicit poses from scratch (no incremental bookkeeping): pose i is
+ * ligand d_lig[i] placed at rigid start d_start[i], then torsion k (sweep
+ * order) turned by step d_steps[i][k] for k < B.  d_steps is [n_poses][16].
+ * Ligands whose status is not OK score +inf; a descriptor whose ligand or
+ * start index is out of range scores NaN.
+ */
+int dock_score_poses(const dock_grid_desc *g, const float *d_grids, const void *d_pack, int32_t n_lig,
+                     int64_t n_atoms_total, const dock_search *s, const int32_t *d_lig, const int32_t *d_start,
+                     const uint16_t *d_steps, int64_t n_poses, float *d_scores, void *stream);
+
+/* Static text for a DOCK_* status code. */
+const char *dock_error_string(int code);
+
+/* Detail of the last failing call on this thread ("" if none). */
+const char *dock_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIGATE_DOCK_H */

@@ -1,0 +1,776 @@
+// The docking screen: rigid starts, greedy torsion sweeps, best pose per ligand.
+//
+// Work decomposition.  A work item is (ligand, batch of rigid starts).  Persistent blocks pop
+// items from an atomic counter; items are ordered by descending estimated cost so the longest
+// ligands start first.  A block stages the item's ligand in LDS and its wavefronts take the
+// item's starts round-robin.  Within a wavefront, lanes are torsion steps: lane L evaluates the
+// angles 2 pi (L + 64 j) / S, j < APL, so one sweep of S angles costs ceil(S / 64) angles per
+// lane and the argmin is a single wave reduction.  Atom coordinates live in registers, atom i
+// (and i + 64) on lane i.
+//
+// Scoring inside a sweep.  Turning torsion k moves only its moving set M_k, so the step that
+// minimises the score also minimises the part that depends on the step: the grid terms of the
+// moving atoms plus the clash of (moving, fixed) pairs.  Each moving atom runs on a circle
+// x(t) = p + a cos t + b sin t about the axis, so a pair distance is d^2(t) = A + C cos t +
+// D sin t; a pair whose closest approach over the whole circle is beyond the clash cut-off
+// cannot contribute and is dropped once per sweep.  The pose score is carried along as
+// E <- E - var(0) + var(s*), starting from the rigid pose (grid terms + the clash of the
+// reference conformer, which rigid motion does not change).
+//
+// The per-ligand best (score, start) is an atomicMin on packed ordered keys, so ties go to the
+// lowest start.  A replay kernel then reruns the winning start with the same code to recover
+// its torsion steps; the result is bitwise identical because every reduction inside a start has
+// a fixed order.
+#include <math.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace ligate {
+
+int grid_desc_check(const dock_grid_desc *g);
+
+struct GridC {
+    const float *__restrict__ G;
+    int nx, ny, nz, nxy, nxyz;
+    float inv_h, ox_h, oy_h, oz_h;  // u = x * inv_h - o / h
+    float mx, my, mz;               // n - 1
+    float cx, cy, cz;               // n - 2
+    float w_h2;                     // w_out * h^2
+};
+
+struct SearchC {
+    const float *__restrict__ quat;
+    const float *__restrict__ trans;
+    int n_quat, n_trans, S, QT;
+    float cut, cut2_keep, w;
+};
+
+struct LigLDS {
+    float xr[DOCK_MAX_ATOMS], yr[DOCK_MAX_ATOMS], zr[DOCK_MAX_ATOMS];
+    int tof[DOCK_MAX_ATOMS];  // type * nodes per grid
+    uint4 excl[DOCK_MAX_ATOMS];
+    TorRec tor[DOCK_MAX_TORSIONS];
+    int n, B, status, lig;
+};
+
+// Circle coefficients of one moving atom for the current sweep.
+struct Coef {
+    float px, py, pz, ax, ay, az, bx, by, bz;
+    int tof;
+    float rho, zz;
+};
+static_assert(sizeof(Coef) == 48, "Coef layout");
+
+constexpr int kSurvCap = 128;
+
+struct WaveLDS {
+    Coef coef[kWave];
+    uint8_t atom[kWave];
+    float4 surv[kSurvCap];
+};
+
+// ---------------------------------------------------------------------------------------------
+// Grid lookup (trilinear; clamp + restraint or periodic)
+// ---------------------------------------------------------------------------------------------
+
+template <int BOUNDARY>
+__device__ __forceinline__ float lookup(const GridC &g, int tof, float x, float y, float z) {
+    const float ux = fmaf(x, g.inv_h, -g.ox_h);
+    const float uy = fmaf(y, g.inv_h, -g.oy_h);
+    const float uz = fmaf(z, g.inv_h, -g.oz_h);
+    if constexpr (BOUNDARY == DOCK_BOUNDARY_CLAMP) {
+        // fmaxf returns the non-NaN operand, so even a NaN coordinate yields an in-range cell
+        const float qx = fminf(fmaxf(ux, 0.0f), g.mx);
+        const float qy = fminf(fmaxf(uy, 0.0f), g.my);
+        const float qz = fminf(fmaxf(uz, 0.0f), g.mz);
+        const float fx0 = floorf(fminf(qx, g.cx)), fy0 = floorf(fminf(qy, g.cy)), fz0 = floorf(fminf(qz, g.cz));
+        const float fx = qx - fx0, fy = qy - fy0, fz = qz - fz0;
+        const int idx = (int)fx0 + g.nx * ((int)fy0 + g.ny * (int)fz0);
+        const float *p0 = g.G + tof + idx;
+        const float *p1 = p0 + g.nxy;
+        const float g000 = p0[0], g100 = p0[1], g010 = p0[g.nx], g110 = p0[g.nx + 1];
+        const float g001 = p1[0], g101 = p1[1], g011 = p1[g.nx], g111 = p1[g.nx + 1];
+        const float c00 = fmaf(fx, g100 - g000, g000), c10 = fmaf(fx, g110 - g010, g010);
+        const float c01 = fmaf(fx, g101 - g001, g001), c11 = fmaf(fx, g111 - g011, g011);
+        const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
+        const float v = fmaf(fz, c1 - c0, c0);
+        const float dx = ux - qx, dy = uy - qy, dz = uz - qz;
+        return fmaf(g.w_h2, fmaf(dx, dx, fmaf(dy, dy, dz * dz)), v);
+    } else {
+        const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
+        const float fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
+        int ix = (int)fx0 % g.nx, iy = (int)fy0 % g.ny, iz = (int)fz0 % g.nz;
+        ix += ix < 0 ? g.nx : 0;
+        iy += iy < 0 ? g.ny : 0;
+        iz += iz < 0 ? g.nz : 0;
+        const int jx = ix + 1 == g.nx ? 0 : ix + 1, jy = iy + 1 == g.ny ? 0 : iy + 1,
+                  jz = iz + 1 == g.nz ? 0 : iz + 1;
+        const float *b = g.G + tof;
+        const int r00 = g.nx * (iy + g.ny * iz), r10 = g.nx * (jy + g.ny * iz);
+        const int r01 = g.nx * (iy + g.ny * jz), r11 = g.nx * (jy + g.ny * jz);
+        const float g000 = b[r00 + ix], g100 = b[r00 + jx], g010 = b[r10 + ix], g110 = b[r10 + jx];
+        const float g001 = b[r01 + ix], g101 = b[r01 + jx], g011 = b[r11 + ix], g111 = b[r11 + jx];
+        const float c00 = fmaf(fx, g100 - g000, g000), c10 = fmaf(fx, g110 - g010, g010);
+        const float c01 = fmaf(fx, g101 - g001, g001), c11 = fmaf(fx, g111 - g011, g011);
+        const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
+        return fmaf(fz, c1 - c0, c0);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Ligand staging and the per-start greedy pass (one wavefront)
+// ---------------------------------------------------------------------------------------------
+
+// Cooperative load of ligand `lig` into LDS by `nthreads` threads; returns nothing, caller syncs.
+__device__ void load_ligand(LigLDS &L, const PackView &pk, int lig, int nxyz, int tid, int nthreads) {
+    const LigDesc d = pk.desc[lig];
+    if (tid == 0) {
+        L.n = d.n;
+        L.B = d.B;
+        L.status = d.status;
+        L.lig = lig;
+    }
+    if (d.status != DOCK_LIG_OK) return;
+    for (int i = tid; i < d.n; i += nthreads) {
+        L.xr[i] = pk.x[d.atom_off + i];
+        L.yr[i] = pk.y[d.atom_off + i];
+        L.zr[i] = pk.z[d.atom_off + i];
+        L.tof[i] = (int)pk.type[d.atom_off + i] * nxyz;
+        L.excl[i] = pk.excl[d.atom_off + i];
+    }
+    for (int k = tid; k < d.B; k += nthreads) L.tor[k] = pk.tor[(size_t)lig * DOCK_MAX_TORSIONS + k];
+}
+
+// Clash energy of the reference conformer (pairs three or more bonds apart), summed over the wave.
+__device__ float rigid_clash(const LigLDS &L, const SearchC &s) {
+    const int lane = lane_id();
+    float acc = 0.0f;
+    for (int i = 0; i < L.n; ++i) {
+        const float xi = L.xr[i], yi = L.yr[i], zi = L.zr[i];
+        const uint4 ex = L.excl[i];
+        for (int j = i + 1 + lane; j < L.n; j += kWave) {
+            if (mask_has(ex, j)) continue;
+            const float dx = L.xr[j] - xi, dy = L.yr[j] - yi, dz = L.zr[j] - zi;
+            const float d = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+            const float t = fmaxf(s.cut - d, 0.0f);
+            acc = fmaf(s.w * t, t, acc);
+        }
+    }
+    return wave_sum(acc);
+}
+
+__device__ __forceinline__ float shfl_f(float v, int src) { return __shfl(v, src); }
+
+// Circle coefficients of the atom at `x` for the axis through `xa` with unit direction `u`.
+__device__ __forceinline__ void circle(float ux, float uy, float uz, float xax, float xay, float xaz, float x, float y,
+                                       float z, float &px, float &py, float &pz, float &ax, float &ay, float &az,
+                                       float &bx, float &by, float &bz) {
+    const float vx = x - xax, vy = y - xay, vz = z - xaz;
+    const float zz = fmaf(ux, vx, fmaf(uy, vy, uz * vz));
+    px = fmaf(zz, ux, xax);
+    py = fmaf(zz, uy, xay);
+    pz = fmaf(zz, uz, xaz);
+    ax = fmaf(-zz, ux, vx);
+    ay = fmaf(-zz, uy, vy);
+    az = fmaf(-zz, uz, vz);
+    bx = uy * vz - uz * vy;
+    by = uz * vx - ux * vz;
+    bz = ux * vy - uy * vx;
+}
+
+// Per-lane cos/sin of the lane's angles 2 pi (lane + 64 j) / S.
+template <int APL>
+__device__ __forceinline__ void angle_table(int S, float (&cs)[APL], float (&sn)[APL]) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int j = 0; j < APL; ++j) {
+        const int st = lane + kWave * j;
+        float sv, cv;
+        sincospif(2.0f * (float)st / (float)S, &sv, &cv);
+        cs[j] = cv;
+        sn[j] = sv;
+    }
+}
+
+// One greedy pass from rigid start p.  Returns the final score (identical on all lanes);
+// lane k (< B) receives the step chosen for torsion k in `my_step`.
+template <int APL, int BOUNDARY>
+__device__ float run_start(const GridC &g, const SearchC &s, const LigLDS &L, WaveLDS &W, int p, float clash_ref,
+                           const float (&cs)[APL], const float (&sn)[APL], int &my_step) {
+    const int lane = lane_id();
+    const int n = L.n;
+    // rigid placement
+    const int iq = p / s.n_trans, it = p - iq * s.n_trans;
+    float qw = s.quat[4 * iq], qx = s.quat[4 * iq + 1], qy = s.quat[4 * iq + 2], qz = s.quat[4 * iq + 3];
+    const float qn = 1.0f / sqrtf(fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz))));
+    qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+    const float r00 = 1.0f - 2.0f * (qy * qy + qz * qz), r01 = 2.0f * (qx * qy - qw * qz), r02 = 2.0f * (qx * qz + qw * qy);
+    const float r10 = 2.0f * (qx * qy + qw * qz), r11 = 1.0f - 2.0f * (qx * qx + qz * qz), r12 = 2.0f * (qy * qz - qw * qx);
+    const float r20 = 2.0f * (qx * qz - qw * qy), r21 = 2.0f * (qy * qz + qw * qx), r22 = 1.0f - 2.0f * (qx * qx + qy * qy);
+    const float tx = s.trans[3 * it], ty = s.trans[3 * it + 1], tz = s.trans[3 * it + 2];
+
+    float cx[2], cy[2], cz[2];
+    float eg = 0.0f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = lane + kWave * h;
+        cx[h] = cy[h] = cz[h] = 0.0f;
+        if (i < n) {
+            const float x = L.xr[i], y = L.yr[i], z = L.zr[i];
+            cx[h] = fmaf(r00, x, fmaf(r01, y, fmaf(r02, z, tx)));
+            cy[h] = fmaf(r10, x, fmaf(r11, y, fmaf(r12, z, ty)));
+            cz[h] = fmaf(r20, x, fmaf(r21, y, fmaf(r22, z, tz)));
+            eg += lookup<BOUNDARY>(g, L.tof[i], cx[h], cy[h], cz[h]);
+        }
+    }
+    float E = wave_sum(eg) + clash_ref;
+
+    for (int k = 0; k < L.B; ++k) {
+        const TorRec tr = L.tor[k];
+        const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
+        const int a = tr.a, b = tr.b;
+        const float xax = shfl_f(a < kWave ? cx[0] : cx[1], a & 63);
+        const float xay = shfl_f(a < kWave ? cy[0] : cy[1], a & 63);
+        const float xaz = shfl_f(a < kWave ? cz[0] : cz[1], a & 63);
+        const float xbx = shfl_f(b < kWave ? cx[0] : cx[1], b & 63);
+        const float xby = shfl_f(b < kWave ? cy[0] : cy[1], b & 63);
+        const float xbz = shfl_f(b < kWave ? cz[0] : cz[1], b & 63);
+        float ux = xbx - xax, uy = xby - xay, uz = xbz - xaz;
+        const float un = 1.0f / sqrtf(fmaf(ux, ux, fmaf(uy, uy, uz * uz)));
+        ux *= un; uy *= un; uz *= un;
+
+        float e[APL];
+#pragma unroll
+        for (int j = 0; j < APL; ++j) e[j] = 0.0f;
+        int nsurv = 0;
+
+        auto flush = [&](int cnt) {
+            for (int q = 0; q < cnt; ++q) {
+                const float4 acd = W.surv[q];
+#pragma unroll
+                for (int j = 0; j < APL; ++j) {
+                    const float d2 = fmaxf(fmaf(acd.y, cs[j], fmaf(acd.z, sn[j], acd.x)), 0.0f);
+                    const float t = fmaxf(s.cut - sqrtf(d2), 0.0f);
+                    e[j] = fmaf(s.w * t, t, e[j]);
+                }
+            }
+        };
+
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (kWave * h >= n) break;
+            const int i = lane + kWave * h;
+            const bool mv = i < n && mask_has(mask, i);
+            const uint64_t bal = __ballot(mv);
+            const int cnt = __popcll(bal);
+            if (mv) {
+                Coef c;
+                circle(ux, uy, uz, xax, xay, xaz, cx[h], cy[h], cz[h], c.px, c.py, c.pz, c.ax, c.ay, c.az, c.bx, c.by,
+                       c.bz);
+                c.tof = L.tof[i];
+                c.rho = sqrtf(fmaf(c.ax, c.ax, fmaf(c.ay, c.ay, c.az * c.az)));
+                c.zz = fmaf(ux, cx[h] - xax, fmaf(uy, cy[h] - xay, uz * (cz[h] - xaz)));
+                const int slot = lanes_below(bal);
+                W.coef[slot] = c;
+                W.atom[slot] = (uint8_t)i;
+            }
+            wave_sync();
+            // grid terms of the moving atoms on their circles
+            for (int q = 0; q < cnt; ++q) {
+                const Coef c = W.coef[q];
+#pragma unroll
+                for (int j = 0; j < APL; ++j) {
+                    const float x = fmaf(c.ax, cs[j], fmaf(c.bx, sn[j], c.px));
+                    const float y = fmaf(c.ay, cs[j], fmaf(c.by, sn[j], c.py));
+                    const float z = fmaf(c.az, cs[j], fmaf(c.bz, sn[j], c.pz));
+                    e[j] += lookup<BOUNDARY>(g, c.tof, x, y, z);
+                }
+            }
+            // (moving, fixed) clash pairs that can come within the cut-off somewhere on the circle
+            for (int q = 0; q < cnt; ++q) {
+                const Coef c = W.coef[q];
+                const uint4 ex = L.excl[W.atom[q]];
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    if (kWave * h2 >= n) break;
+                    const int jj = lane + kWave * h2;
+                    bool keep = false;
+                    float A = 0.0f, C = 0.0f, D = 0.0f;
+                    if (jj < n && !mask_has(mask, jj) && !mask_has(ex, jj)) {
+                        const float vx = cx[h2] - xax, vy = cy[h2] - xay, vz = cz[h2] - xaz;
+                        const float zj = fmaf(ux, vx, fmaf(uy, vy, uz * vz));
+                        const float ox = fmaf(-zj, ux, vx), oy = fmaf(-zj, uy, vy), oz = fmaf(-zj, uz, vz);
+                        const float rj = sqrtf(fmaf(ox, ox, fmaf(oy, oy, oz * oz)));
+                        const float dr = c.rho - rj, dz = c.zz - zj;
+                        keep = fmaf(dr, dr, dz * dz) < s.cut2_keep;
+                        const float wx = c.px - cx[h2], wy = c.py - cy[h2], wz = c.pz - cz[h2];
+                        A = fmaf(wx, wx, fmaf(wy, wy, fmaf(wz, wz, c.rho * c.rho)));
+                        C = 2.0f * fmaf(wx, c.ax, fmaf(wy, c.ay, wz * c.az));
+                        D = 2.0f * fmaf(wx, c.bx, fmaf(wy, c.by, wz * c.bz));
+                    }
+                    const uint64_t kb = __ballot(keep);
+                    if (keep) W.surv[nsurv + lanes_below(kb)] = make_float4(A, C, D, 0.0f);
+                    nsurv += __popcll(kb);
+                    if (nsurv >= kWave) {
+                        wave_sync();
+                        flush(nsurv);
+                        nsurv = 0;
+                        wave_sync();
+                    }
+                }
+            }
+            wave_sync();
+        }
+        if (nsurv) {
+            wave_sync();
+            flush(nsurv);
+            wave_sync();
+        }
+
+        // argmin over the S steps, ties to the lowest step
+        uint64_t best = ~0ull;
+#pragma unroll
+        for (int j = 0; j < APL; ++j) {
+            const int st = lane + kWave * j;
+            if (st < s.S) {
+                const uint64_t key = ((uint64_t)float_to_ordered(e[j]) << 32) | (uint32_t)st;
+                best = key < best ? key : best;
+            }
+        }
+        best = wave_min_u64(best);
+        const int sbest = (int)(uint32_t)best;
+        const float ebest = ordered_to_float((uint32_t)(best >> 32));
+        const float e0 = __shfl(e[0], 0);
+        E += ebest - e0;
+
+        // apply the winning step
+        const int jb = sbest / kWave, owner = sbest - jb * kWave;
+        float csel = cs[0], ssel = sn[0];
+#pragma unroll
+        for (int j = 1; j < APL; ++j)
+            if (j == jb) {
+                csel = cs[j];
+                ssel = sn[j];
+            }
+        const float cb = __shfl(csel, owner), sb = __shfl(ssel, owner);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = lane + kWave * h;
+            if (i < n && mask_has(mask, i)) {
+                float px, py, pz, ax, ay, az, bx, by, bz;
+                circle(ux, uy, uz, xax, xay, xaz, cx[h], cy[h], cz[h], px, py, pz, ax, ay, az, bx, by, bz);
+                cx[h] = fmaf(ax, cb, fmaf(bx, sb, px));
+                cy[h] = fmaf(ay, cb, fmaf(by, sb, py));
+                cz[h] = fmaf(az, cb, fmaf(bz, sb, pz));
+            }
+        }
+        if (lane == k) my_step = sbest;
+    }
+    return E;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------------------------
+
+struct ScreenArgs {
+    GridC g;
+    SearchC s;
+    PackView pk;
+    const uint64_t *order;   // cost-sorted keys, ligand index in the low 32 bits
+    uint64_t *best_key;      // [n_lig]
+    uint32_t *counter;
+    float *start_scores;     // optional [n_lig][QT]
+    int n_lig, P, bpl, nw;
+    int64_t n_items;
+};
+
+__global__ void k_screen_init(uint64_t *best_key, int n_lig, uint32_t *counter, uint64_t *pose_count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_lig) best_key[i] = ~0ull;
+    if (i == 0) {
+        *counter = 0u;
+        if (pose_count) *pose_count = 0ull;
+    }
+}
+
+// Planner: cost-descending order (ties by ligand index); invalid ligands last.
+__global__ void k_screen_plan(const LigDesc *desc, int n_lig, int S, uint64_t *keys, uint64_t *pose_count, int QT) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t poses = 0;
+    if (l < n_lig) {
+        const LigDesc d = desc[l];
+        uint64_t cost = 0;
+        if (d.status == DOCK_LIG_OK) {
+            cost = (uint64_t)d.n + (uint64_t)(S - 1) * (uint64_t)d.sum_m + (uint64_t)d.n_pairs;
+            poses = (uint64_t)QT * (1ull + (uint64_t)d.B * (uint64_t)(S - 1));
+        }
+        if (cost > 0xffffffffull) cost = 0xffffffffull;
+        keys[l] = ((uint64_t)(~(uint32_t)cost) << 32) | (uint32_t)l;
+    }
+    if (pose_count) {
+        // per-wave partial sums, one atomic per wave
+        uint32_t lo = (uint32_t)poses, hi = (uint32_t)(poses >> 32);
+        uint64_t tot = 0;
+        for (int src = 0; src < kWave; ++src)
+            tot += ((uint64_t)(uint32_t)__shfl((int)hi, src) << 32) | (uint32_t)__shfl((int)lo, src);
+        if (lane_id() == 0 && tot) atomicAdd((unsigned long long *)pose_count, (unsigned long long)tot);
+    }
+}
+
+template <int APL, int BOUNDARY>
+__global__ __launch_bounds__(512) void k_screen(ScreenArgs A) {
+    extern __shared__ __align__(16) char smem[];
+    LigLDS &L = *reinterpret_cast<LigLDS *>(smem);
+    WaveLDS *Wv = reinterpret_cast<WaveLDS *>(smem + ((sizeof(LigLDS) + 15) & ~size_t(15)));
+    __shared__ int item_s;
+    __shared__ uint64_t wbest_s[8];
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    WaveLDS &W = Wv[w];
+    float cs[APL], sn[APL];
+    angle_table<APL>(A.s.S, cs, sn);
+
+    for (;;) {
+        if (tid == 0) item_s = (int)atomicAdd(A.counter, 1u);
+        __syncthreads();
+        const int64_t item = item_s;
+        if (item >= A.n_items) break;
+        const int slot = (int)(item / A.bpl), batch = (int)(item - (int64_t)slot * A.bpl);
+        const int lig = (int)(uint32_t)A.order[slot];
+        load_ligand(L, A.pk, lig, A.g.nxyz, tid, blockDim.x);
+        __syncthreads();
+        if (L.status == DOCK_LIG_OK) {
+            const float clash_ref = rigid_clash(L, A.s);
+            uint64_t wbest = ~0ull;
+            const int p0 = batch * A.P, p1 = min(p0 + A.P, A.s.QT);
+            for (int p = p0 + w; p < p1; p += A.nw) {
+                int step = 0;
+                const float E = run_start<APL, BOUNDARY>(A.g, A.s, L, W, p, clash_ref, cs, sn, step);
+                const uint64_t key = ((uint64_t)float_to_ordered(E) << 32) | (uint32_t)p;
+                wbest = key < wbest ? key : wbest;
+                if (A.start_scores && lane == 0) A.start_scores[(size_t)lig * A.s.QT + p] = E;
+            }
+            if (lane == 0) wbest_s[w] = wbest;
+        }
+        __syncthreads();
+        if (tid == 0 && L.status == DOCK_LIG_OK) {
+            uint64_t b = wbest_s[0];
+            for (int q = 1; q < A.nw; ++q) b = wbest_s[q] < b ? wbest_s[q] : b;
+            atomicMin((unsigned long long *)&A.best_key[lig], (unsigned long long)b);
+        }
+        __syncthreads();
+    }
+}
+
+// Reruns each ligand's winning start to recover its torsion steps, then writes the outputs.
+template <int APL, int BOUNDARY>
+__global__ __launch_bounds__(64) void k_replay(ScreenArgs A, float *best_score, int32_t *best_start,
+                                               uint16_t *best_steps) {
+    extern __shared__ __align__(16) char smem[];
+    LigLDS &L = *reinterpret_cast<LigLDS *>(smem);
+    WaveLDS &W = *reinterpret_cast<WaveLDS *>(smem + ((sizeof(LigLDS) + 15) & ~size_t(15)));
+    const int lig = blockIdx.x, lane = lane_id();
+    float cs[APL], sn[APL];
+    angle_table<APL>(A.s.S, cs, sn);
+    load_ligand(L, A.pk, lig, A.g.nxyz, lane, kWave);
+    __syncthreads();
+    const uint64_t key = A.best_key[lig];
+    int step = 0;
+    float E = INFINITY;
+    int p = -1;
+    if (L.status == DOCK_LIG_OK && key != ~0ull) {
+        p = (int)(uint32_t)key;
+        const float clash_ref = rigid_clash(L, A.s);
+        E = run_start<APL, BOUNDARY>(A.g, A.s, L, W, p, clash_ref, cs, sn, step);
+    }
+    if (lane < DOCK_MAX_TORSIONS) best_steps[(size_t)lig * DOCK_MAX_TORSIONS + lane] =
+        (uint16_t)(p >= 0 && lane < L.B ? step : 0);
+    if (lane == 0) {
+        best_score[lig] = E;
+        best_start[lig] = p;
+    }
+}
+
+// Scores explicit poses from scratch: place, apply the given steps, full grid + clash sum.
+template <int BOUNDARY>
+__global__ __launch_bounds__(64) void k_score_poses(GridC g, SearchC s, PackView pk, int n_lig, const int32_t *d_lig,
+                                                    const int32_t *d_start, const uint16_t *d_steps, int64_t n_poses,
+                                                    float *out) {
+    __shared__ LigLDS L;
+    const int64_t pose = blockIdx.x;
+    const int lane = lane_id();
+    const int lig = d_lig[pose];
+    const int p = d_start[pose];
+    if (lig < 0 || lig >= n_lig || p < 0 || p >= s.QT) {  // descriptor outside the library or start set
+        if (lane == 0) out[pose] = NAN;
+        return;
+    }
+    load_ligand(L, pk, lig, g.nxyz, lane, kWave);
+    __syncthreads();
+    if (L.status != DOCK_LIG_OK) {
+        if (lane == 0) out[pose] = INFINITY;
+        return;
+    }
+    const int n = L.n;
+    const int iq = p / s.n_trans, it = p - iq * s.n_trans;
+    float qw = s.quat[4 * iq], qx = s.quat[4 * iq + 1], qy = s.quat[4 * iq + 2], qz = s.quat[4 * iq + 3];
+    const float qn = 1.0f / sqrtf(fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz))));
+    qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+    const float r00 = 1.0f - 2.0f * (qy * qy + qz * qz), r01 = 2.0f * (qx * qy - qw * qz), r02 = 2.0f * (qx * qz + qw * qy);
+    const float r10 = 2.0f * (qx * qy + qw * qz), r11 = 1.0f - 2.0f * (qx * qx + qz * qz), r12 = 2.0f * (qy * qz - qw * qx);
+    const float r20 = 2.0f * (qx * qz - qw * qy), r21 = 2.0f * (qy * qz + qw * qx), r22 = 1.0f - 2.0f * (qx * qx + qy * qy);
+    const float tx = s.trans[3 * it], ty = s.trans[3 * it + 1], tz = s.trans[3 * it + 2];
+    float cx[2], cy[2], cz[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = lane + kWave * h;
+        cx[h] = cy[h] = cz[h] = 0.0f;
+        if (i < n) {
+            const float x = L.xr[i], y = L.yr[i], z = L.zr[i];
+            cx[h] = fmaf(r00, x, fmaf(r01, y, fmaf(r02, z, tx)));
+            cy[h] = fmaf(r10, x, fmaf(r11, y, fmaf(r12, z, ty)));
+            cz[h] = fmaf(r20, x, fmaf(r21, y, fmaf(r22, z, tz)));
+        }
+    }
+    for (int k = 0; k < L.B; ++k) {
+        const TorRec tr = L.tor[k];
+        const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
+        const int a = tr.a, b = tr.b;
+        const float xax = __shfl(a < kWave ? cx[0] : cx[1], a & 63);
+        const float xay = __shfl(a < kWave ? cy[0] : cy[1], a & 63);
+        const float xaz = __shfl(a < kWave ? cz[0] : cz[1], a & 63);
+        const float xbx = __shfl(b < kWave ? cx[0] : cx[1], b & 63);
+        const float xby = __shfl(b < kWave ? cy[0] : cy[1], b & 63);
+        const float xbz = __shfl(b < kWave ? cz[0] : cz[1], b & 63);
+        float ux = xbx - xax, uy = xby - xay, uz = xbz - xaz;
+        const float un = 1.0f / sqrtf(fmaf(ux, ux, fmaf(uy, uy, uz * uz)));
+        ux *= un; uy *= un; uz *= un;
+        const int st = d_steps[pose * DOCK_MAX_TORSIONS + k];
+        float sb, cb;
+        sincospif(2.0f * (float)st / (float)s.S, &sb, &cb);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = lane + kWave * h;
+            if (i < n && mask_has(mask, i)) {
+                float px, py, pz, ax, ay, az, bx, by, bz;
+                circle(ux, uy, uz, xax, xay, xaz, cx[h], cy[h], cz[h], px, py, pz, ax, ay, az, bx, by, bz);
+                cx[h] = fmaf(ax, cb, fmaf(bx, sb, px));
+                cy[h] = fmaf(ay, cb, fmaf(by, sb, py));
+                cz[h] = fmaf(az, cb, fmaf(bz, sb, pz));
+            }
+        }
+    }
+    float acc = 0.0f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = lane + kWave * h;
+        if (i < n) acc += lookup<BOUNDARY>(g, L.tof[i], cx[h], cy[h], cz[h]);
+    }
+    for (int i = 0; i < n; ++i) {
+        const float xi = __shfl(i < kWave ? cx[0] : cx[1], i & 63);
+        const float yi = __shfl(i < kWave ? cy[0] : cy[1], i & 63);
+        const float zi = __shfl(i < kWave ? cz[0] : cz[1], i & 63);
+        const uint4 ex = L.excl[i];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = lane + kWave * h;
+            if (j > i && j < n && !mask_has(ex, j)) {
+                const float dx = cx[h] - xi, dy = cy[h] - yi, dz = cz[h] - zi;
+                const float d = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+                const float t = fmaxf(s.cut - d, 0.0f);
+                acc = fmaf(s.w * t, t, acc);
+            }
+        }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) out[pose] = acc;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------------------------
+
+static GridC make_grid(const dock_grid_desc *d, const float *G) {
+    GridC g;
+    g.G = G;
+    g.nx = d->nx;
+    g.ny = d->ny;
+    g.nz = d->nz;
+    g.nxy = d->nx * d->ny;
+    g.nxyz = d->nx * d->ny * d->nz;
+    g.inv_h = 1.0f / d->spacing;
+    g.ox_h = d->origin[0] / d->spacing;
+    g.oy_h = d->origin[1] / d->spacing;
+    g.oz_h = d->origin[2] / d->spacing;
+    g.mx = (float)(d->nx - 1);
+    g.my = (float)(d->ny - 1);
+    g.mz = (float)(d->nz - 1);
+    g.cx = (float)(d->nx - 2);
+    g.cy = (float)(d->ny - 2);
+    g.cz = (float)(d->nz - 2);
+    g.w_h2 = d->w_out * d->spacing * d->spacing;
+    return g;
+}
+
+static int check_search(const dock_search *s) {
+    LIGATE_REQUIRE(s != nullptr, DOCK_ERR_INVALID_ARG, "search is NULL");
+    LIGATE_REQUIRE(s->n_quat >= 1 && s->n_trans >= 1 && s->d_quat && s->d_trans, DOCK_ERR_INVALID_ARG,
+                   "empty or NULL start sets");
+    LIGATE_REQUIRE((int64_t)s->n_quat * s->n_trans < (1ll << 31), DOCK_ERR_LIMIT, "too many starts");
+    LIGATE_REQUIRE(s->n_steps >= 1 && s->n_steps <= DOCK_MAX_STEPS, DOCK_ERR_LIMIT, "n_steps must be in [1, 1024]");
+    LIGATE_REQUIRE(s->clash_cut >= 0.0f && s->clash_w >= 0.0f, DOCK_ERR_INVALID_ARG, "negative clash parameters");
+    LIGATE_REQUIRE(s->starts_per_item >= 0 && s->waves_per_block >= 0 && s->waves_per_block <= 8,
+                   DOCK_ERR_INVALID_ARG, "bad tuning fields");
+    return DOCK_OK;
+}
+
+static SearchC make_search(const dock_search *d) {
+    SearchC s;
+    s.quat = d->d_quat;
+    s.trans = d->d_trans;
+    s.n_quat = d->n_quat;
+    s.n_trans = d->n_trans;
+    s.S = d->n_steps;
+    s.QT = d->n_quat * d->n_trans;
+    s.cut = d->clash_cut;
+    const float keep = d->clash_cut + 1e-3f;
+    s.cut2_keep = keep * keep;
+    s.w = d->clash_w;
+    return s;
+}
+
+static size_t al(size_t v) { return (v + 255) & ~size_t(255); }
+
+static size_t screen_lds(int nw) { return ((sizeof(LigLDS) + 15) & ~size_t(15)) + sizeof(WaveLDS) * (size_t)nw; }
+
+template <int APL, int BOUNDARY>
+static int launch_screen(const ScreenArgs &A, float *bs, int32_t *bp, uint16_t *bst, hipStream_t st) {
+    static int cu = 0;
+    if (cu == 0) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cu <= 0) cu = 256;
+    }
+    const size_t lds = screen_lds(A.nw);
+    int per_cu = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_screen<APL, BOUNDARY>),
+                                                 kWave * A.nw, lds);
+    if (per_cu <= 0) per_cu = 1;
+    const int64_t blocks = std::min<int64_t>(A.n_items, (int64_t)cu * per_cu);
+    if (blocks > 0)
+        hipLaunchKernelGGL((k_screen<APL, BOUNDARY>), dim3((unsigned)blocks), dim3(kWave * A.nw), lds, st, A);
+    hipLaunchKernelGGL((k_replay<APL, BOUNDARY>), dim3((unsigned)A.n_lig), dim3(kWave), screen_lds(1), st, A, bs, bp,
+                       bst);
+    return check_launch("dock_screen");
+}
+
+template <int BOUNDARY>
+static int dispatch_apl(int S, const ScreenArgs &A, float *bs, int32_t *bp, uint16_t *bst, hipStream_t st) {
+    if (S <= 64) return launch_screen<1, BOUNDARY>(A, bs, bp, bst, st);
+    if (S <= 128) return launch_screen<2, BOUNDARY>(A, bs, bp, bst, st);
+    if (S <= 256) return launch_screen<4, BOUNDARY>(A, bs, bp, bst, st);
+    if (S <= 512) return launch_screen<8, BOUNDARY>(A, bs, bp, bst, st);
+    return launch_screen<16, BOUNDARY>(A, bs, bp, bst, st);
+}
+
+static int default_cu_count() {
+    int dev = 0, cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    return cu > 0 ? cu : 256;
+}
+
+}  // namespace ligate
+
+using namespace ligate;
+
+extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const void *d_pack, int32_t n_lig,
+                           int64_t n_atoms_total, const dock_search *sd, float *d_best_score, int32_t *d_best_start,
+                           uint16_t *d_best_steps, float *d_start_scores, uint64_t *d_pose_count, void *d_ws,
+                           size_t *ws_bytes, void *stream) {
+    int rc = grid_desc_check(gd);
+    if (rc) return rc;
+    rc = check_search(sd);
+    if (rc) return rc;
+    LIGATE_REQUIRE(n_lig >= 1 && n_atoms_total >= 0 && n_atoms_total < (1ll << 31), DOCK_ERR_INVALID_ARG,
+                   "bad library size");
+    LIGATE_REQUIRE(ws_bytes != nullptr, DOCK_ERR_INVALID_ARG, "ws_bytes is NULL");
+    const size_t need = al(8 * (size_t)n_lig) + al(8 * (size_t)n_lig) + al(256) + radix_sort_ws_bytes(n_lig);
+    if (d_ws == nullptr) {
+        *ws_bytes = need;
+        return DOCK_OK;
+    }
+    LIGATE_REQUIRE(*ws_bytes >= need, DOCK_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", *ws_bytes, need);
+    LIGATE_REQUIRE(d_grids && d_pack && d_best_score && d_best_start && d_best_steps, DOCK_ERR_INVALID_ARG,
+                   "NULL array");
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)d_ws;
+    uint64_t *best_key = (uint64_t *)w;
+    uint64_t *order = (uint64_t *)(w + al(8 * (size_t)n_lig));
+    uint32_t *counter = (uint32_t *)(w + 2 * al(8 * (size_t)n_lig));
+    void *rws = w + 2 * al(8 * (size_t)n_lig) + al(256);
+
+    ScreenArgs A;
+    A.g = make_grid(gd, d_grids);
+    A.g.G = d_grids;
+    A.s = make_search(sd);
+    A.pk = PackView::of(d_pack, n_lig, n_atoms_total);
+    A.order = order;
+    A.best_key = best_key;
+    A.counter = counter;
+    A.start_scores = d_start_scores;
+    A.n_lig = n_lig;
+    A.nw = sd->waves_per_block ? sd->waves_per_block : 4;
+    LIGATE_REQUIRE(A.nw == 1 || A.nw == 2 || A.nw == 4 || A.nw == 8, DOCK_ERR_INVALID_ARG,
+                   "waves_per_block must be 1, 2, 4 or 8");
+    int P = sd->starts_per_item;
+    if (P == 0) {
+        // enough items to keep every block busy several times over, at most 256 starts per item
+        const int64_t slots = (int64_t)default_cu_count() * 6;
+        const int64_t total = (int64_t)n_lig * A.s.QT;
+        int64_t want = total / (4 * slots);
+        want = std::max<int64_t>(A.nw, std::min<int64_t>(256, want));
+        P = (int)want;
+    }
+    P = std::min(P, A.s.QT);
+    A.P = P;
+    A.bpl = (A.s.QT + P - 1) / P;
+    A.n_items = (int64_t)n_lig * A.bpl;
+
+    const unsigned nb = (unsigned)((n_lig + 255) / 256);
+    hipLaunchKernelGGL(k_screen_init, dim3(nb), dim3(256), 0, st, best_key, n_lig, counter, d_pose_count);
+    hipLaunchKernelGGL(k_screen_plan, dim3(nb), dim3(256), 0, st, A.pk.desc, n_lig, A.s.S, order, d_pose_count,
+                       A.s.QT);
+    rc = radix_sort_u64(order, n_lig, 32, 64, rws, st);
+    if (rc) return rc;
+    if (gd->boundary == DOCK_BOUNDARY_PERIODIC)
+        return dispatch_apl<DOCK_BOUNDARY_PERIODIC>(A.s.S, A, d_best_score, d_best_start, d_best_steps, st);
+    return dispatch_apl<DOCK_BOUNDARY_CLAMP>(A.s.S, A, d_best_score, d_best_start, d_best_steps, st);
+}
+
+extern "C" int dock_score_poses(const dock_grid_desc *gd, const float *d_grids, const void *d_pack, int32_t n_lig,
+                                int64_t n_atoms_total, const dock_search *sd, const int32_t *d_lig,
+                                const int32_t *d_start, const uint16_t *d_steps, int64_t n_poses, float *d_scores,
+                                void *stream) {
+    int rc = grid_desc_check(gd);
+    if (rc) return rc;
+    rc = check_search(sd);
+    if (rc) return rc;
+    LIGATE_REQUIRE(n_lig >= 1 && n_poses >= 0 && n_poses < (1ll << 31), DOCK_ERR_INVALID_ARG, "bad sizes");
+    if (n_poses == 0) return DOCK_OK;
+    LIGATE_REQUIRE(d_grids && d_pack && d_lig && d_start && d_steps && d_scores, DOCK_ERR_INVALID_ARG, "NULL array");
+    const GridC g = make_grid(gd, d_grids);
+    const SearchC s = make_search(sd);
+    const PackView pk = PackView::of(d_pack, n_lig, n_atoms_total);
+    hipStream_t st = (hipStream_t)stream;
+    if (gd->boundary == DOCK_BOUNDARY_PERIODIC)
+        hipLaunchKernelGGL(k_score_poses<DOCK_BOUNDARY_PERIODIC>, dim3((unsigned)n_poses), dim3(kWave), 0, st, g, s,
+                           pk, n_lig, d_lig, d_start, d_steps, n_poses, d_scores);
+    else
+        hipLaunchKernelGGL(k_score_poses<DOCK_BOUNDARY_CLAMP>, dim3((unsigned)n_poses), dim3(kWave), 0, st, g, s, pk,
+                           n_lig, d_lig, d_start, d_steps, n_poses, d_scores);
+    return check_launch("dock_score_poses");
+}

@@ -1,0 +1,147 @@
+"""Device-side driver of the docking screen: buffers and the order of the ABI calls.
+
+Holds PyTorch device tensors (memory and streams only) and calls the C ABI in
+``dock.py``; every step of the computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import dock
+
+
+def _dev(a, device, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(device).contiguous()
+
+
+class DevicePocket:
+    """Receptor grids built on the device by ``dock_build_grids``."""
+
+    def __init__(self, pocket, device="cuda", boundary: int = dock.BOUNDARY_CLAMP, stream=None):
+        self.pocket = pocket
+        self.desc = dock.grid_desc(pocket, boundary)
+        nbytes = dock.grid_bytes(self.desc)
+        self.grids = torch.empty(nbytes // 4, dtype=torch.float32, device=device)
+        self.prot_xyz = _dev(pocket.prot_xyz, device, torch.float32)
+        self.prot_type = _dev(pocket.prot_type, device, torch.int32)
+        dock.build_grids(self.desc, self.prot_xyz, self.prot_type, pocket.type_R, pocket.type_eps, pocket.type_q,
+                         pocket.cap, pocket.r_min, pocket.coulomb_k, self.grids, stream)
+
+    def view(self):
+        nx, ny, nz = self.pocket.dims
+        return self.grids.view(self.pocket.n_types, nz, ny, nx)
+
+
+class DeviceLibrary:
+    """A ligand library copied to the device and packed by ``dock_pack_ligands``."""
+
+    def __init__(self, ligs, device="cuda", stream=None):
+        self.n_lig = ligs.n_lig
+        self.n_atoms = int(ligs.atom_off[-1])
+        self.n_types = ligs.n_types
+        self.atom_off = _dev(ligs.atom_off, device, torch.int32)
+        self.xyz = _dev(ligs.xyz.reshape(-1), device, torch.float32)
+        self.types = _dev(ligs.types, device, torch.uint8)
+        self.bond_off = _dev(ligs.bond_off, device, torch.int32)
+        self.bonds = _dev(ligs.bonds.reshape(-1), device, torch.int32)
+        self.rot = _dev(ligs.rot, device, torch.uint8)
+        if self.bonds.numel() == 0:  # keep valid pointers for libraries of single atoms
+            self.bonds = torch.zeros(2, dtype=torch.int32, device=device)
+            self.rot = torch.zeros(1, dtype=torch.uint8, device=device)
+        nbytes = dock.pack_bytes(self.n_lig, self.n_atoms, self.n_types)
+        self.pack = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.status = torch.empty(self.n_lig, dtype=torch.int32, device=device)
+        dock.pack_ligands(self.atom_off, self.xyz, self.types, self.bond_off, self.bonds, self.rot, self.n_types,
+                          self.pack, self.status, stream)
+
+    def descriptors(self) -> dict:
+        """Per-ligand (n, B, status, sum of moving-set sizes, clash pairs) as written by the packer.
+        The packed library opens with an array of 32-byte records of eight int32."""
+        raw = self.pack[:32 * self.n_lig].cpu().numpy().view(np.int32).reshape(self.n_lig, 8)
+        return {"n": raw[:, 1].copy(), "B": raw[:, 2].copy(), "status": raw[:, 3].copy(),
+                "sum_m": raw[:, 4].copy(), "n_pairs": raw[:, 5].copy()}
+
+
+class DeviceSearch:
+    def __init__(self, search, device="cuda", starts_per_item: int = 0, waves_per_block: int = 0):
+        self.search = search
+        self.quat = _dev(search.quat, device, torch.float32)
+        self.trans = _dev(search.trans, device, torch.float32)
+        self.desc = dock.search_desc(self.quat, self.trans, search.n_steps, search.clash_cut, search.clash_w,
+                                     starts_per_item, waves_per_block)
+
+    @property
+    def n_starts(self) -> int:
+        return self.quat.shape[0] * self.trans.shape[0]
+
+
+@dataclass
+class ScreenResult:
+    best_score: torch.Tensor   # float32 [n_lig]
+    best_start: torch.Tensor   # int32 [n_lig]
+    best_steps: torch.Tensor   # uint16 [n_lig, 16] (as int32 view on the host)
+    pose_count: torch.Tensor   # uint64 [1] (int64 storage)
+    start_scores: torch.Tensor | None
+
+
+class Screener:
+    """Runs ``dock_screen`` for one (pocket, library, search) with preallocated outputs."""
+
+    def __init__(self, pocket: DevicePocket, lib: DeviceLibrary, search: DeviceSearch, start_scores: bool = False):
+        self.pocket, self.lib, self.search = pocket, lib, search
+        dev = pocket.grids.device
+        n = lib.n_lig
+        self.ws = torch.empty(dock.screen_ws_bytes(pocket.desc, n, lib.n_atoms, search.desc), dtype=torch.uint8,
+                              device=dev)
+        self.best_score = torch.empty(n, dtype=torch.float32, device=dev)
+        self.best_start = torch.empty(n, dtype=torch.int32, device=dev)
+        self.best_steps = torch.empty(n * dock.MAX_TORSIONS, dtype=torch.int16, device=dev)
+        self.pose_count = torch.empty(1, dtype=torch.int64, device=dev)
+        self.start_scores = (torch.empty(n * search.n_starts, dtype=torch.float32, device=dev)
+                             if start_scores else None)
+
+    def run(self, stream=None) -> ScreenResult:
+        dock.screen(self.pocket.desc, self.pocket.grids, self.lib.pack, self.lib.n_lig, self.lib.n_atoms,
+                    self.search.desc, self.best_score, self.best_start, self.best_steps, self.ws,
+                    self.start_scores, self.pose_count, stream)
+        return ScreenResult(self.best_score, self.best_start, self.best_steps.view(self.lib.n_lig, -1),
+                            self.pose_count, self.start_scores)
+
+
+def screen(pocket: DevicePocket, lib: DeviceLibrary, search: DeviceSearch, start_scores: bool = False):
+    return Screener(pocket, lib, search, start_scores).run()
+
+
+def topk(scores: torch.Tensor, k: int, ids: torch.Tensor | None = None, stream=None):
+    n = scores.numel()
+    dev = scores.device
+    ws = torch.empty(dock.topk_ws_bytes(n, k), dtype=torch.uint8, device=dev)
+    out_s = torch.empty(k, dtype=torch.float32, device=dev)
+    out_i = torch.empty(k, dtype=torch.int32, device=dev)
+    dock.topk(scores, k, out_s, out_i, ws, ids, stream)
+    return out_s, out_i
+
+
+def score_poses(pocket: DevicePocket, lib: DeviceLibrary, search: DeviceSearch, lig, start, steps, stream=None):
+    dev = pocket.grids.device
+    lig = _dev(lig, dev, torch.int32)
+    start = _dev(start, dev, torch.int32)
+    st = np.zeros((len(lig), dock.MAX_TORSIONS), np.int16)
+    steps = np.asarray(steps).reshape(len(lig), -1)
+    st[:, :steps.shape[1]] = steps
+    st = _dev(st.reshape(-1), dev, torch.int16)
+    out = torch.empty(len(lig), dtype=torch.float32, device=dev)
+    dock.score_poses(pocket.desc, pocket.grids, lib.pack, lib.n_lig, lib.n_atoms, search.desc, lig, start, st, out,
+                     stream)
+    return out
+
+
+def steps_numpy(best_steps: torch.Tensor) -> np.ndarray:
+    """uint16 steps stored in int16 tensors -> int32 array."""
+    return best_steps.cpu().numpy().astype(np.int32) & 0xFFFF

@@ -1,0 +1,98 @@
+"""The C ABI library loads, exports every declared symbol, and rejects bad arguments on the host.
+
+No GPU is needed: argument validation and size queries return before any HIP call.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ligate_dock.h")
+
+
+def _lib():
+    from paper_2304_09953_amd import build
+    if not os.path.exists(build.LIB_PATH):
+        build.build_library()
+    from paper_2304_09953_amd import dock
+    return dock, dock.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(dock_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for n in ("dock_build_grids", "dock_pack_ligands", "dock_screen", "dock_topk", "dock_grid_bytes",
+              "dock_score_poses", "dock_error_string", "dock_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    dock, lib = _lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(dock.EXPORTS) == set(declared_functions())
+
+
+def test_error_strings():
+    dock, lib = _lib()
+    assert lib.dock_error_string(0) == b"ok"
+    assert b"workspace" in lib.dock_error_string(-4)
+
+
+def _desc(dock, **kw):
+    d = dict(nx=8, ny=9, nz=10, n_types=4, origin=(ctypes.c_float * 3)(0, 0, 0), spacing=0.375, layout=0,
+             boundary=0, w_out=10.0)
+    d.update(kw)
+    return dock.GridDesc(**d)
+
+
+def test_grid_desc_validation():
+    dock, lib = _lib()
+    out = ctypes.c_size_t()
+    assert lib.dock_grid_bytes(ctypes.byref(_desc(dock)), ctypes.byref(out)) == 0
+    assert out.value == 4 * 4 * 8 * 9 * 10
+    for bad in (dict(nx=1), dict(spacing=0.0), dict(layout=3), dict(boundary=7)):
+        assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, **bad)), ctypes.byref(out)) == -1
+        assert lib.dock_last_error() != b""
+    assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, n_types=33)), ctypes.byref(out)) == -2
+    assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, nx=300, ny=300, nz=300)), ctypes.byref(out)) == -2
+
+
+def test_size_queries_and_argument_errors():
+    dock, lib = _lib()
+    sz = ctypes.c_size_t()
+    assert lib.dock_pack_ligands(None, None, None, None, None, None, 10, 300, 16, None, ctypes.byref(sz), None,
+                                 None) == 0
+    assert sz.value > 300 * 12
+    assert lib.dock_pack_ligands(None, None, None, None, None, None, -1, 300, 16, None, ctypes.byref(sz), None,
+                                 None) == -1
+    assert lib.dock_pack_ligands(None, None, None, None, None, None, 10, 300, 40, None, ctypes.byref(sz), None,
+                                 None) == -2
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: size queries return before any device work
+    s = dock.SearchDesc(4, fake, 2, fake, 64, 2.5, 10.0, 0, 0)
+    assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(s), None, None, None, None,
+                           None, None, ctypes.byref(sz), None) == 0
+    assert sz.value > 0
+    s_bad = dock.SearchDesc(4, fake, 2, fake, 2048, 2.5, 10.0, 0, 0)
+    assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(s_bad), None, None, None, None,
+                           None, None, ctypes.byref(sz), None) == -2
+    assert lib.dock_topk(None, None, 100, 10, None, None, None, ctypes.byref(sz), None) == 0
+    assert lib.dock_topk(None, None, 100, 101, None, None, None, ctypes.byref(sz), None) == -1
+    assert lib.dock_topk(None, None, 0, 1, None, None, None, ctypes.byref(sz), None) == -1
+    # a workspace smaller than the query is refused before anything is enqueued
+    small = ctypes.c_size_t(16)
+    assert lib.dock_topk(fake, None, 100, 10, fake, fake, fake, ctypes.byref(small), None) == -4
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2304_09953_amd import dock
+    monkeypatch.setattr(dock, "_lib", None)
+    monkeypatch.setattr(dock, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(dock.DockError):
+        dock.load()
