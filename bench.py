@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--n-lig", type=int, default=None, help="dock only the first N ligands (a subset workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the library is sharded by "
@@ -91,8 +93,17 @@ def main():
     from paper_2304_09953_amd import pipeline as P
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "launches": 1}), flush=True)
+        return
     dock.load()  # fails loudly if the HIP library is missing
-    W = I.config(2)
+    W = I.workload("pocket96-lib100k")
     n_lig = args.n_lig or W.n_lig
     log(f"generating {n_lig} ligands")
     ligs = W.ligands(n_lig=n_lig)
@@ -162,9 +173,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": ("config2" if n_lig == W.n_lig else f"config2 subset, first {n_lig} ligands")
-                   + ": 96^3 x 16-type grid, 300 protein atoms; ligands n~N(35,10) in [15,70], B~Poisson(5) in "
-                     "[0,12]; 256 quaternions x 32 translations, 256 torsion steps; top-1000",
+        "config": {"workload": (W.name if n_lig == W.n_lig else f"first {n_lig} ligands of " + W.name)
+                   + "; top-1000",
                    "n_lig": n_lig, "grid": "96^3x16", "search": "Q256xT32xS256", "top_k": k},
         "poses_per_sec": poses * args.steps / dt,
         "screen_ms": screen_ms,

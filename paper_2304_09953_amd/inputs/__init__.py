@@ -6,16 +6,17 @@ the HIP path and the CPU oracle consume the arrays it returns.  The heavy liftin
 every ligand has its own counter-keyed random stream, so ligand ``g`` of a
 library is the same whichever chunk it is generated in.
 
-Workloads (the shapes of the paper's screening campaigns, §2 and §3.3; all
-sizes below are the published benchmark configurations of this port):
+Workloads (synthetic stand-ins for the screening campaigns of §2 and the
+batched, uneven libraries of §3.3):
 
-* ``config1``: one 48^3 pocket with 8 atom types, 100 ligands of exactly 24
-  atoms and 4 rotatable bonds; 64 quaternions x 8 translations, 64 steps.
-* ``config2``: one 96^3 pocket with 16 types, 100k ligands with atom counts
-  N(35, 10) clipped to [15, 70] and Poisson(5) rotatable bonds clipped to
-  [0, 12]; 256 quaternions x 32 translations, 256 steps.
-* ``config3``: four pockets of 64^3, 80^3, 96^3 and 128^3, 250k ligands of
-  which 5 % have 80-120 atoms; config-2 search.
+* ``pocket48-lib100``: one 48^3 pocket with 8 atom types, 100 ligands of
+  exactly 24 atoms and 4 rotatable bonds; 64 quaternions x 8 translations,
+  64 torsion steps.
+* ``pocket96-lib100k``: one 96^3 pocket with 16 types, 100k ligands with atom
+  counts N(35, 10) clipped to [15, 70] and Poisson(5) rotatable bonds clipped
+  to [0, 12]; 256 quaternions x 32 translations, 256 steps.
+* ``pockets4-lib250k``: four pockets of 64^3, 80^3, 96^3 and 128^3, 250k
+  ligands of which 5 % have 80-120 atoms; the 100k-library search.
 """
 from __future__ import annotations
 
@@ -100,9 +101,9 @@ class LibDist:
                           n_types, self.offset_range)
 
 
-DIST_CONFIG1 = LibDist(fixed_n=24, fixed_b=4)
-DIST_CONFIG2 = LibDist()
-DIST_CONFIG3 = LibDist(tail_p=0.05)
+DIST_FIXED24 = LibDist(fixed_n=24, fixed_b=4)
+DIST_DRUGLIKE = LibDist()
+DIST_HEAVY_TAIL = LibDist(tail_p=0.05)
 DIST_TINY = LibDist(n_mean=6.0, n_sd=1.5, n_min=4, n_max=8, b_mean=1.5, b_max=3)
 
 
@@ -294,21 +295,25 @@ class Workload:
         return make_ligands(self.n_lig if n_lig is None else n_lig, self.dist, self.n_types, stream, first_id)
 
 
-def config(k: int) -> Workload:
-    if k == 1:
+def workload(name: str) -> Workload:
+    """The benchmark workloads, named by their sizes."""
+    if name == "pocket48-lib100":
         p = make_pocket(48, 8)
-        return Workload("config1: 48^3x8 grid, 100 ligands n=24 B=4, Q64xT8 S64", [p],
-                        make_search(64, 8, 64, 2.0, p.center), DIST_CONFIG1, 100, 8)
-    if k == 2:
+        return Workload("pocket48-lib100: 48^3 x 8-type grid, 100 ligands of 24 atoms with 4 rotatable bonds; "
+                        "64 quaternions x 8 translations, 64 torsion steps", [p],
+                        make_search(64, 8, 64, 2.0, p.center), DIST_FIXED24, 100, 8)
+    if name == "pocket96-lib100k":
         p = make_pocket(96, 16)
-        return Workload("config2: 96^3x16 grid, 100k ligands n~N(35,10) B~Poisson(5), Q256xT32 S256", [p],
-                        make_search(256, 32, 256, 4.0, p.center), DIST_CONFIG2, 100_000, 16)
-    if k == 3:
+        return Workload("pocket96-lib100k: 96^3 x 16-type grid, 100k ligands n~N(35,10) in [15,70], "
+                        "B~Poisson(5) in [0,12]; 256 quaternions x 32 translations, 256 torsion steps", [p],
+                        make_search(256, 32, 256, 4.0, p.center), DIST_DRUGLIKE, 100_000, 16)
+    if name == "pockets4-lib250k":
         ps = [make_pocket(d, 16, pocket_id=i) for i, d in enumerate((64, 80, 96, 128))]
-        return Workload("config3: 4 pockets 64^3..128^3 x16, 250k ligands 5% at 80-120 atoms, top-1000", ps,
-                        make_search(256, 32, 256, 4.0, ps[0].center), DIST_CONFIG3, 250_000, 16,
+        return Workload("pockets4-lib250k: 64^3, 80^3, 96^3 and 128^3 x 16-type grids, 250k ligands of which 5% "
+                        "have 80-120 atoms; 256 x 32 starts, 256 steps; top-1000 per pocket", ps,
+                        make_search(256, 32, 256, 4.0, ps[0].center), DIST_HEAVY_TAIL, 250_000, 16,
                         {"top_k": 1000})
-    raise ValueError(k)
+    raise ValueError(f"unknown workload {name!r}")
 
 
 def search_for(pocket: Pocket, base: Search, radius: float = 4.0) -> Search:

@@ -28,17 +28,17 @@ _ensure_cpu_libs()
 
 
 @pytest.fixture(scope="session")
-def cfg1():
+def p48():
     from paper_2304_09953_amd import inputs as I
-    return I.config(1)
+    return I.workload("pocket48-lib100")
 
 
 @pytest.fixture(scope="session")
-def cfg1_grid(cfg1):
+def p48_grid(p48):
     import oracle
-    return oracle.build_grids(cfg1.pockets[0])
+    return oracle.build_grids(p48.pockets[0])
 
 
 @pytest.fixture(scope="session")
-def cfg1_ligs(cfg1):
-    return cfg1.ligands()
+def p48_ligs(p48):
+    return p48.ligands()

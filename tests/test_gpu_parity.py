@@ -28,10 +28,10 @@ def P():
 
 
 @pytest.fixture(scope="module")
-def c1(P):
-    W = I.config(1)
+def p48(P):
+    W = I.workload("pocket48-lib100")
     pocket = W.pockets[0]
-    say("config1 grids")
+    say("48^3 pocket grids")
     dp = P.DevicePocket(pocket)
     return W, pocket, dp, oracle.build_grids(pocket), W.ligands()
 
@@ -40,11 +40,11 @@ def c1(P):
 # Grids
 # ------------------------------------------------------------------------------------------------
 
-def test_grids_config1_match_oracle(c1):
-    W, pocket, dp, G, _ = c1
+def test_grids_pocket48_match_oracle(p48):
+    W, pocket, dp, G, _ = p48
     g = dp.view().cpu().numpy()
     err = np.abs(g.astype(np.float64) - G) / np.maximum(1.0, np.abs(G))
-    say(f"config1 grid max rel err {err.max():.3g}")
+    say(f"48^3 grid max rel err {err.max():.3g}")
     assert err.max() <= 1e-6
 
 
@@ -94,7 +94,7 @@ def _mask_bits(words, n):
 def _edge_library():
     from test_oracle_pins import chain
     parts = []
-    for src, idx in ((I.make_ligands(30, I.DIST_CONFIG3, 16, stream="test"), range(30)),
+    for src, idx in ((I.make_ligands(30, I.DIST_HEAVY_TAIL, 16, stream="test"), range(30)),
                      (I.make_ligands(3, I.LibDist(fixed_n=128, fixed_b=16, b_max=16), 16, stream="test"), range(3)),
                      (I.make_ligands(3, I.LibDist(fixed_n=100, fixed_b=12), 16, stream="test"), range(3))):
         parts += [src.ligand(i) for i in idx]
@@ -146,14 +146,14 @@ def test_pack_status_topology_and_centring(P):
 # Pose scoring
 # ------------------------------------------------------------------------------------------------
 
-def test_score_poses_vs_oracle(P, c1):
-    W, pocket, dp, G, ligs = c1
+def test_score_poses_vs_oracle(P, p48):
+    W, pocket, dp, G, ligs = p48
     rng = np.random.default_rng(3)
     n = 3000
     lig = rng.integers(0, ligs.n_lig, n)
     start = rng.integers(0, W.search.n_starts, n)
     steps = rng.integers(0, W.search.n_steps, (n, 4))
-    say("score_poses config1 3000 random poses")
+    say("score_poses pocket48-lib100, 3000 random poses")
     lib = P.DeviceLibrary(ligs)
     ds = P.DeviceSearch(W.search)
     got = P.score_poses(dp, lib, ds, lig, start, steps).cpu().numpy()
@@ -180,9 +180,9 @@ def _screen(P, dp, ligs, search, start_scores=False, **kw):
     return out
 
 
-def test_screen_config1_full(P, c1):
-    W, pocket, dp, G, ligs = c1
-    say("screen config1 (100 ligands, 512 starts, S=64) with per-start scores")
+def test_screen_pocket48_lib100_full(P, p48):
+    W, pocket, dp, G, ligs = p48
+    say("screen pocket48-lib100 (100 ligands, 512 starts, S=64) with per-start scores")
     g = _screen(P, dp, ligs, W.search, start_scores=True)
     orc = oracle.dock(pocket, G, ligs, W.search, per_start=True)
     st = check_per_start(g["finals"], orc, ligs.n_atoms)
@@ -236,13 +236,13 @@ def test_screen_edge_cases(P):
         assert g["poses"] == oracle.pose_count(ligs.n_rot, st, srch.n_starts, S)
 
 
-def test_screen_is_deterministic_and_tuning_invariant(P, c1):
-    W, pocket, dp, G, ligs = c1
+def test_screen_is_deterministic_and_tuning_invariant(P, p48):
+    W, pocket, dp, G, ligs = p48
     sub = ligs.subset(np.arange(0, 100, 9))
     runs = []
     for kw in ({}, {"starts_per_item": 3, "waves_per_block": 1}, {"starts_per_item": 64, "waves_per_block": 8},
                {"starts_per_item": 512, "waves_per_block": 2}, {}):
-        say(f"screen config1 subset tuning {kw}")
+        say(f"screen pocket48-lib100 subset, tuning {kw}")
         runs.append(_screen(P, dp, sub, W.search, start_scores=True, **kw))
     for r in runs[1:]:
         for key in ("score", "start", "steps", "finals"):
@@ -252,7 +252,7 @@ def test_screen_is_deterministic_and_tuning_invariant(P, c1):
 def test_periodic_boundary_translation_covariance(P):
     pocket = I.make_pocket(40, 4, pocket_id=11)
     G = oracle.build_grids(pocket)
-    ligs = I.make_ligands(16, I.DIST_CONFIG2, 4, stream="test")
+    ligs = I.make_ligands(16, I.DIST_DRUGLIKE, 4, stream="test")
     srch = I.make_search(4, 3, 16, 3.0, pocket.center)
     say("periodic boundary: GPU vs oracle and roll covariance")
     dp = P.DevicePocket(pocket, boundary=1)
@@ -305,8 +305,8 @@ def test_topk_vs_oracle(P, n, k, with_ids):
 # Full-size configuration 2 (96^3 x 16 grid, 256 x 32 starts, S = 256) on a stratified sample
 # ------------------------------------------------------------------------------------------------
 
-def test_config2_sample_full_search(P):
-    W = I.config(2)
+def test_pocket96_lib100k_sample_full_search(P):
+    W = I.workload("pocket96-lib100k")
     pocket = W.pockets[0]
     lib_all = W.ligands(n_lig=20000)
     n, b = lib_all.n_atoms, lib_all.n_rot
@@ -318,12 +318,12 @@ def test_config2_sample_full_search(P):
     pick |= set(small.tolist())
     sel = np.array(sorted(pick))
     ligs = lib_all.subset(sel)
-    say(f"config2 sample of {len(sel)} ligands, 96^3 grid, full search, bench launch configuration")
+    say(f"pocket96-lib100k sample of {len(sel)} ligands, 96^3 grid, full search, bench launch configuration")
     dp = P.DevicePocket(pocket)
     G = oracle.build_grids(pocket)  # the oracle's own grid
     g = _screen(P, dp, ligs, W.search, starts_per_item=256, waves_per_block=4)
     e = check_exact_and_valid(pocket, G, ligs, W.search, np.arange(len(sel)), g["score"], g["start"], g["steps"])
-    say(f"config2 sample: rescoring max rel err {e:.3g}")
+    say(f"pocket96 sample: rescoring max rel err {e:.3g}")
     # optimality on the small ligands with a full oracle run
     loc = np.array([int(np.flatnonzero(sel == s)[0]) for s in small])
     orc = oracle.dock(pocket, G, ligs, W.search, sel=loc, per_start=True)

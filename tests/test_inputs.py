@@ -6,19 +6,19 @@ from paper_2304_09953_amd import inputs as I
 
 
 def test_ligand_is_independent_of_chunking():
-    a = I.make_ligands(50, I.DIST_CONFIG2, 16, first_id=1000)
-    b = I.make_ligands(20, I.DIST_CONFIG2, 16, first_id=1030)
+    a = I.make_ligands(50, I.DIST_DRUGLIKE, 16, first_id=1000)
+    b = I.make_ligands(20, I.DIST_DRUGLIKE, 16, first_id=1030)
     for j in range(20):
         xa, ta, ba, ra = a.ligand(30 + j)
         xb, tb, bb, rb = b.ligand(j)
         assert np.array_equal(xa, xb) and np.array_equal(ta, tb)
         assert np.array_equal(ba, bb) and np.array_equal(ra, rb)
-    c = I.make_ligands(50, I.DIST_CONFIG2, 16, first_id=1000, stream="train")
+    c = I.make_ligands(50, I.DIST_DRUGLIKE, 16, first_id=1000, stream="train")
     assert not np.array_equal(a.xyz[:100], c.xyz[:100])
 
 
 def test_generated_trees_are_valid_and_clash_free():
-    ligs = I.make_ligands(300, I.DIST_CONFIG3, 16, stream="test")
+    ligs = I.make_ligands(300, I.DIST_HEAVY_TAIL, 16, stream="test")
     assert np.all(oracle.status(ligs) == 0)
     for l in range(0, 300, 7):
         x, t, b, r = ligs.ligand(l)
@@ -32,15 +32,15 @@ def test_generated_trees_are_valid_and_clash_free():
         assert np.all(t < 16)
 
 
-def test_config_distributions():
-    l2 = I.make_ligands(20000, I.DIST_CONFIG2, 16)
+def test_library_distributions():
+    l2 = I.make_ligands(20000, I.DIST_DRUGLIKE, 16)
     n, b = l2.n_atoms, l2.n_rot
     assert n.min() >= 15 and n.max() <= 70 and abs(n.mean() - 35.0) < 0.3
     assert b.min() >= 0 and b.max() <= 12 and abs(b.mean() - 5.0) < 0.15
-    l3 = I.make_ligands(20000, I.DIST_CONFIG3, 16)
+    l3 = I.make_ligands(20000, I.DIST_HEAVY_TAIL, 16)
     heavy = l3.n_atoms >= 80
     assert abs(heavy.mean() - 0.05) < 0.006 and l3.n_atoms.max() <= 120
-    l1 = I.make_ligands(100, I.DIST_CONFIG1, 8)
+    l1 = I.make_ligands(100, I.DIST_FIXED24, 8)
     assert np.all(l1.n_atoms == 24) and np.all(l1.n_rot == 4)
     # type weights proportional to 1/(1+t)
     w = 1.0 / (1.0 + np.arange(16))

@@ -251,7 +251,7 @@ def test_topology_chain_orientation_core_and_order():
 
 
 def test_topology_relabelled_moving_sets_are_descendants():
-    ligs = I.make_ligands(40, I.DIST_CONFIG2, 16, stream="test")
+    ligs = I.make_ligands(40, I.DIST_DRUGLIKE, 16, stream="test")
     for l in range(40):
         t = oracle.topology(ligs, l)
         _, _, bonds, rot = ligs.ligand(l)
@@ -280,7 +280,7 @@ def _fragments(n, bonds, rot):
 
 
 def test_clash_pairs_match_shortest_paths():
-    ligs = I.make_ligands(30, I.DIST_CONFIG3, 16, stream="test")
+    ligs = I.make_ligands(30, I.DIST_HEAVY_TAIL, 16, stream="test")
     for l in range(30):
         t = oracle.topology(ligs, l)
         _, _, bonds, _ = ligs.ligand(l)
@@ -329,18 +329,18 @@ def _dist(X):
     return np.linalg.norm(X[:, None, :] - X[None, :, :], axis=-1)
 
 
-def test_rigid_start_preserves_shape_and_centres_on_translation(cfg1, cfg1_ligs):
-    s = cfg1.search
+def test_rigid_start_preserves_shape_and_centres_on_translation(p48, p48_ligs):
+    s = p48.search
     for l in (0, 7):
-        xyz = cfg1_ligs.ligand(l)[0].astype(np.float64)
+        xyz = p48_ligs.ligand(l)[0].astype(np.float64)
         for p in (0, 5, 300, 511):
-            X = oracle.pose_coords(cfg1_ligs, s, l, p, upto=0)
+            X = oracle.pose_coords(p48_ligs, s, l, p, upto=0)
             assert np.allclose(_dist(X), _dist(xyz), atol=1e-12)
             assert np.allclose(X.mean(0), s.trans[p % len(s.trans)], atol=1e-12)
 
 
 def test_torsion_move_invariants():
-    ligs = I.make_ligands(20, I.DIST_CONFIG2, 16, stream="test")
+    ligs = I.make_ligands(20, I.DIST_DRUGLIKE, 16, stream="test")
     srch = I.make_search(4, 2, 16, 2.0, [0, 0, 0])
     for l in range(20):
         t = oracle.topology(ligs, l)
@@ -369,16 +369,16 @@ def test_torsion_move_invariants():
         assert np.allclose(X, X0)
 
 
-def test_score_is_lookups_plus_clash(cfg1, cfg1_grid, cfg1_ligs):
-    p, s = cfg1.pockets[0], cfg1.search
+def test_score_is_lookups_plus_clash(p48, p48_grid, p48_ligs):
+    p, s = p48.pockets[0], p48.search
     for l in range(5):
-        t = oracle.topology(cfg1_ligs, l)
-        types = cfg1_ligs.ligand(l)[1]
-        X = oracle.pose_coords(cfg1_ligs, s, l, 17 * l, RNG.integers(0, 64, size=4))
+        t = oracle.topology(p48_ligs, l)
+        types = p48_ligs.ligand(l)[1]
+        X = oracle.pose_coords(p48_ligs, s, l, 17 * l, RNG.integers(0, 64, size=4))
         X = X + RNG.normal(scale=0.3, size=X.shape)  # also unphysical geometry with clashes
         d = np.linalg.norm(X[t["pairs"][:, 0]] - X[t["pairs"][:, 1]], axis=1)
-        ref = oracle.lookup_points(p, cfg1_grid, types, X).sum() + 10.0 * np.sum(np.maximum(0, 2.5 - d) ** 2)
-        assert oracle.score_conformer(p, cfg1_grid, cfg1_ligs, s, l, X) == pytest.approx(ref, rel=1e-12)
+        ref = oracle.lookup_points(p, p48_grid, types, X).sum() + 10.0 * np.sum(np.maximum(0, 2.5 - d) ** 2)
+        assert oracle.score_conformer(p, p48_grid, p48_ligs, s, l, X) == pytest.approx(ref, rel=1e-12)
 
 
 def test_clash_closed_form_and_rigid_invariance():
