@@ -145,14 +145,15 @@ int dock_pack_ligands(const int32_t *d_atom_off, const float *d_xyz, const uint8
  * d_best_start [n_lig] (-1 if not OK), d_best_steps [n_lig][16] (the chosen
  * step of each torsion in sweep order, unused entries 0), optional
  * d_start_scores [n_lig][n_quat*n_trans] (final score of every start; NULL to
- * skip), optional d_pose_count [1] (distinct poses scored: per docked ligand
- * n_quat*n_trans*(1 + B*(n_steps-1))).  n_lig and n_atoms_total must match the
+ * skip), optional d_start_steps [n_lig][n_quat*n_trans][16] (the steps every
+ * start chose; NULL to skip), optional d_pose_count [1] (distinct poses scored:
+ * per docked ligand n_quat*n_trans*(1 + B*(n_steps-1))).  n_lig and n_atoms_total must match the
  * pack.  Workspace: query with d_ws == NULL.
  */
 int dock_screen(const dock_grid_desc *g, const float *d_grids, const void *d_pack, int32_t n_lig,
                 int64_t n_atoms_total, const dock_search *s, float *d_best_score, int32_t *d_best_start,
-                uint16_t *d_best_steps, float *d_start_scores, uint64_t *d_pose_count, void *d_ws,
-                size_t *ws_bytes, void *stream);
+                uint16_t *d_best_steps, float *d_start_scores, uint16_t *d_start_steps, uint64_t *d_pose_count,
+                void *d_ws, size_t *ws_bytes, void *stream);
 
 /*
  * Ranks scores: the k lowest, ties to the lower id, NaN ranked as +inf;

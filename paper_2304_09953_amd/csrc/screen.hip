@@ -32,36 +32,43 @@ namespace ligate {
 int grid_desc_check(const dock_grid_desc *g);
 
 struct GridC {
-    const float *__restrict__ G;
-    int nx, ny, nz, nxy, nxyz;
-    float inv_h, ox_h, oy_h, oz_h;  // u = x * inv_h - o / h
-    float mx, my, mz;               // n - 1
-    float cx, cy, cz;               // n - 2
-    float w_h2;                     // w_out * h^2
+    const float *G;
+    uint32_t total_bytes;      // all type grids
+    int nx, ny, nz;
+    uint32_t nx4, nxy4;        // byte strides of y and z
+    float fnx4, fnxy4;         // the same as floats; offsets below 2^26 are exact in FP32
+    float mx, my, mz;          // n - 1: clamp bound
+    float cx, cy, cz;          // n - 2: last cell
+    float inv_h, ox_h, oy_h, oz_h;  // grid units: u = x / h - o / h
+    float w_h2;                // restraint weight in grid units (w_out h^2)
 };
 
 struct SearchC {
     const float *__restrict__ quat;
     const float *__restrict__ trans;
     int n_quat, n_trans, S, QT;
-    float cut, cut2_keep, w;
+    float cut, cut2_keep, w;   // clash in grid units: cut-off / h, (cut-off / h + margin)^2, weight h^2
 };
 
+// Coordinates inside a start are in grid units (x - origin) / spacing throughout: the map is a
+// similarity, so rotations and torsion turns commute with it, lookups need no conversion, and the
+// clash is evaluated with the cut-off divided by h and the weight multiplied by h^2.
 struct LigLDS {
-    float xr[DOCK_MAX_ATOMS], yr[DOCK_MAX_ATOMS], zr[DOCK_MAX_ATOMS];
-    int tof[DOCK_MAX_ATOMS];  // type * nodes per grid
+    float xr[DOCK_MAX_ATOMS], yr[DOCK_MAX_ATOMS], zr[DOCK_MAX_ATOMS];  // centred reference / h
+    uint32_t tof[DOCK_MAX_ATOMS];  // byte offset of the atom's type grid
     uint4 excl[DOCK_MAX_ATOMS];
     TorRec tor[DOCK_MAX_TORSIONS];
     int n, B, status, lig;
 };
 
-// Circle coefficients of one moving atom for the current sweep.
+// Circle coefficients of one moving atom for the current sweep (grid units).
 struct Coef {
     float px, py, pz, ax, ay, az, bx, by, bz;
-    int tof;
+    uint32_t tof;  // type grid byte offset; bit 31 set when the whole circle lies inside the box
     float rho, zz;
 };
 static_assert(sizeof(Coef) == 48, "Coef layout");
+constexpr uint32_t kInside = 0x80000000u;
 
 constexpr int kSurvCap = 128;
 
@@ -75,29 +82,92 @@ struct WaveLDS {
 // Grid lookup (trilinear; clamp + restraint or periodic)
 // ---------------------------------------------------------------------------------------------
 
-template <int BOUNDARY>
-__device__ __forceinline__ float lookup(const GridC &g, int tof, float x, float y, float z) {
-    const float ux = fmaf(x, g.inv_h, -g.ox_h);
-    const float uy = fmaf(y, g.inv_h, -g.oy_h);
-    const float uz = fmaf(z, g.inv_h, -g.oz_h);
-    if constexpr (BOUNDARY == DOCK_BOUNDARY_CLAMP) {
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+__device__ __forceinline__ rsrc_t grid_rsrc(const GridC &g) {
+    // raw buffer over all type grids; loads outside it return 0 instead of faulting
+    return __builtin_amdgcn_make_buffer_rsrc((void *)g.G, 0, (int)g.total_bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float2 ld2(rsrc_t rs, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
+}
+
+__device__ __forceinline__ float ld1(rsrc_t rs, uint32_t voff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, 0, 0));
+}
+
+// Trilinear interpolation as linear interpolations along x, then y, then z; a/b are the x pairs
+// of rows (y0, z0)/(y1, z0), c/d of rows (y0, z1)/(y1, z1).
+__device__ __forceinline__ float trilerp(float fx, float fy, float fz, float2 a, float2 b, float2 c, float2 d) {
+    const float c00 = fmaf(fx, a.y - a.x, a.x), c10 = fmaf(fx, b.y - b.x, b.x);
+    const float c01 = fmaf(fx, c.y - c.x, c.x), c11 = fmaf(fx, d.y - d.x, d.x);
+    const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
+    return fmaf(fz, c1 - c0, c0);
+}
+
+// Cell byte offset and fractions of grid point u.  INSIDE: the caller guarantees
+// 0 <= u <= n - 1 - margin, where clamping is the identity and the restraint vanishes, so both
+// variants give the same value there.
+template <bool INSIDE>
+__device__ __forceinline__ uint32_t cell(const GridC &g, float ux, float uy, float uz, float &fx, float &fy, float &fz,
+                                         float &rest) {
+    float qx = ux, qy = uy, qz = uz, x0, y0, z0;
+    if constexpr (INSIDE) {
+        x0 = floorf(qx);
+        y0 = floorf(qy);
+        z0 = floorf(qz);
+        rest = 0.0f;
+    } else {
         // fmaxf returns the non-NaN operand, so even a NaN coordinate yields an in-range cell
-        const float qx = fminf(fmaxf(ux, 0.0f), g.mx);
-        const float qy = fminf(fmaxf(uy, 0.0f), g.my);
-        const float qz = fminf(fmaxf(uz, 0.0f), g.mz);
-        const float fx0 = floorf(fminf(qx, g.cx)), fy0 = floorf(fminf(qy, g.cy)), fz0 = floorf(fminf(qz, g.cz));
-        const float fx = qx - fx0, fy = qy - fy0, fz = qz - fz0;
-        const int idx = (int)fx0 + g.nx * ((int)fy0 + g.ny * (int)fz0);
-        const float *p0 = g.G + tof + idx;
-        const float *p1 = p0 + g.nxy;
-        const float g000 = p0[0], g100 = p0[1], g010 = p0[g.nx], g110 = p0[g.nx + 1];
-        const float g001 = p1[0], g101 = p1[1], g011 = p1[g.nx], g111 = p1[g.nx + 1];
-        const float c00 = fmaf(fx, g100 - g000, g000), c10 = fmaf(fx, g110 - g010, g010);
-        const float c01 = fmaf(fx, g101 - g001, g001), c11 = fmaf(fx, g111 - g011, g011);
-        const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
-        const float v = fmaf(fz, c1 - c0, c0);
+        qx = fminf(fmaxf(ux, 0.0f), g.mx);
+        qy = fminf(fmaxf(uy, 0.0f), g.my);
+        qz = fminf(fmaxf(uz, 0.0f), g.mz);
+        x0 = floorf(fminf(qx, g.cx));
+        y0 = floorf(fminf(qy, g.cy));
+        z0 = floorf(fminf(qz, g.cz));
         const float dx = ux - qx, dy = uy - qy, dz = uz - qz;
-        return fmaf(g.w_h2, fmaf(dx, dx, fmaf(dy, dy, dz * dz)), v);
+        rest = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    }
+    fx = qx - x0;
+    fy = qy - y0;
+    fz = qz - z0;
+    return (uint32_t)fmaf(z0, g.fnxy4, fmaf(y0, g.fnx4, 4.0f * x0));
+}
+
+// N clamp-mode lookups whose type offsets are wave-uniform (sof, SGPRs); all N cells' loads are
+// issued before any is consumed.
+template <int N, bool INSIDE>
+__device__ __forceinline__ void lookup_group(const GridC &g, rsrc_t rs, const uint32_t (&sof)[N], const float (&ux)[N],
+                                             const float (&uy)[N], const float (&uz)[N], float (&out)[N]) {
+    uint32_t off[N];
+    float fx[N], fy[N], fz[N], rest[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) off[k] = cell<INSIDE>(g, ux[k], uy[k], uz[k], fx[k], fy[k], fz[k], rest[k]);
+    float2 a[N], b[N], c[N], d[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        a[k] = ld2(rs, off[k], sof[k]);
+        b[k] = ld2(rs, off[k], sof[k] + g.nx4);
+        c[k] = ld2(rs, off[k], sof[k] + g.nxy4);
+        d[k] = ld2(rs, off[k], sof[k] + g.nxy4 + g.nx4);
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const float v = trilerp(fx[k], fy[k], fz[k], a[k], b[k], c[k], d[k]);
+        out[k] = INSIDE ? v : fmaf(g.w_h2, rest[k], v);
+    }
+}
+
+// One lookup whose type offset differs between lanes (rigid placement, pose scoring).
+template <int BOUNDARY>
+__device__ __forceinline__ float lookup_lane(const GridC &g, rsrc_t rs, uint32_t tof, float ux, float uy, float uz) {
+    if constexpr (BOUNDARY == DOCK_BOUNDARY_CLAMP) {
+        float fx, fy, fz, rest;
+        const uint32_t off = cell<false>(g, ux, uy, uz, fx, fy, fz, rest) + tof;
+        const float2 a = ld2(rs, off, 0), b = ld2(rs, off, g.nx4), c = ld2(rs, off, g.nxy4),
+                     d = ld2(rs, off, g.nxy4 + g.nx4);
+        return fmaf(g.w_h2, rest, trilerp(fx, fy, fz, a, b, c, d));
     } else {
         const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
         const float fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
@@ -107,15 +177,15 @@ __device__ __forceinline__ float lookup(const GridC &g, int tof, float x, float 
         iz += iz < 0 ? g.nz : 0;
         const int jx = ix + 1 == g.nx ? 0 : ix + 1, jy = iy + 1 == g.ny ? 0 : iy + 1,
                   jz = iz + 1 == g.nz ? 0 : iz + 1;
-        const float *b = g.G + tof;
-        const int r00 = g.nx * (iy + g.ny * iz), r10 = g.nx * (jy + g.ny * iz);
-        const int r01 = g.nx * (iy + g.ny * jz), r11 = g.nx * (jy + g.ny * jz);
-        const float g000 = b[r00 + ix], g100 = b[r00 + jx], g010 = b[r10 + ix], g110 = b[r10 + jx];
-        const float g001 = b[r01 + ix], g101 = b[r01 + jx], g011 = b[r11 + ix], g111 = b[r11 + jx];
-        const float c00 = fmaf(fx, g100 - g000, g000), c10 = fmaf(fx, g110 - g010, g010);
-        const float c01 = fmaf(fx, g101 - g001, g001), c11 = fmaf(fx, g111 - g011, g011);
-        const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
-        return fmaf(fz, c1 - c0, c0);
+        const uint32_t r00 = tof + 4u * (uint32_t)(g.nx * (iy + g.ny * iz));
+        const uint32_t r10 = tof + 4u * (uint32_t)(g.nx * (jy + g.ny * iz));
+        const uint32_t r01 = tof + 4u * (uint32_t)(g.nx * (iy + g.ny * jz));
+        const uint32_t r11 = tof + 4u * (uint32_t)(g.nx * (jy + g.ny * jz));
+        const float2 a = make_float2(ld1(rs, r00 + 4 * ix), ld1(rs, r00 + 4 * jx));
+        const float2 b = make_float2(ld1(rs, r10 + 4 * ix), ld1(rs, r10 + 4 * jx));
+        const float2 c = make_float2(ld1(rs, r01 + 4 * ix), ld1(rs, r01 + 4 * jx));
+        const float2 d = make_float2(ld1(rs, r11 + 4 * ix), ld1(rs, r11 + 4 * jx));
+        return trilerp(fx, fy, fz, a, b, c, d);
     }
 }
 
@@ -123,8 +193,8 @@ __device__ __forceinline__ float lookup(const GridC &g, int tof, float x, float 
 // Ligand staging and the per-start greedy pass (one wavefront)
 // ---------------------------------------------------------------------------------------------
 
-// Cooperative load of ligand `lig` into LDS by `nthreads` threads; returns nothing, caller syncs.
-__device__ void load_ligand(LigLDS &L, const PackView &pk, int lig, int nxyz, int tid, int nthreads) {
+// Cooperative load of ligand `lig` into LDS by `nthreads` threads; the caller syncs.
+__device__ void load_ligand(LigLDS &L, const PackView &pk, int lig, const GridC &g, int tid, int nthreads) {
     const LigDesc d = pk.desc[lig];
     if (tid == 0) {
         L.n = d.n;
@@ -133,11 +203,12 @@ __device__ void load_ligand(LigLDS &L, const PackView &pk, int lig, int nxyz, in
         L.lig = lig;
     }
     if (d.status != DOCK_LIG_OK) return;
+    const uint32_t tbytes = 4u * (uint32_t)g.nx * (uint32_t)g.ny * (uint32_t)g.nz;
     for (int i = tid; i < d.n; i += nthreads) {
-        L.xr[i] = pk.x[d.atom_off + i];
-        L.yr[i] = pk.y[d.atom_off + i];
-        L.zr[i] = pk.z[d.atom_off + i];
-        L.tof[i] = (int)pk.type[d.atom_off + i] * nxyz;
+        L.xr[i] = pk.x[d.atom_off + i] * g.inv_h;
+        L.yr[i] = pk.y[d.atom_off + i] * g.inv_h;
+        L.zr[i] = pk.z[d.atom_off + i] * g.inv_h;
+        L.tof[i] = (uint32_t)pk.type[d.atom_off + i] * tbytes;
         L.excl[i] = pk.excl[d.atom_off + i];
     }
     for (int k = tid; k < d.B; k += nthreads) L.tor[k] = pk.tor[(size_t)lig * DOCK_MAX_TORSIONS + k];
@@ -153,7 +224,7 @@ __device__ float rigid_clash(const LigLDS &L, const SearchC &s) {
         for (int j = i + 1 + lane; j < L.n; j += kWave) {
             if (mask_has(ex, j)) continue;
             const float dx = L.xr[j] - xi, dy = L.yr[j] - yi, dz = L.zr[j] - zi;
-            const float d = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+            const float d = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
             const float t = fmaxf(s.cut - d, 0.0f);
             acc = fmaf(s.w * t, t, acc);
         }
@@ -194,14 +265,10 @@ __device__ __forceinline__ void angle_table(int S, float (&cs)[APL], float (&sn)
     }
 }
 
-// One greedy pass from rigid start p.  Returns the final score (identical on all lanes);
-// lane k (< B) receives the step chosen for torsion k in `my_step`.
-template <int APL, int BOUNDARY>
-__device__ float run_start(const GridC &g, const SearchC &s, const LigLDS &L, WaveLDS &W, int p, float clash_ref,
-                           const float (&cs)[APL], const float (&sn)[APL], int &my_step) {
+// Rigid start p in grid units: quaternion rotation of the reference, then the translation.
+__device__ __forceinline__ void place(const GridC &g, const SearchC &s, const LigLDS &L, int p, float (&cx)[2],
+                                      float (&cy)[2], float (&cz)[2]) {
     const int lane = lane_id();
-    const int n = L.n;
-    // rigid placement
     const int iq = p / s.n_trans, it = p - iq * s.n_trans;
     float qw = s.quat[4 * iq], qx = s.quat[4 * iq + 1], qy = s.quat[4 * iq + 2], qz = s.quat[4 * iq + 3];
     const float qn = 1.0f / sqrtf(fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz))));
@@ -209,37 +276,103 @@ __device__ float run_start(const GridC &g, const SearchC &s, const LigLDS &L, Wa
     const float r00 = 1.0f - 2.0f * (qy * qy + qz * qz), r01 = 2.0f * (qx * qy - qw * qz), r02 = 2.0f * (qx * qz + qw * qy);
     const float r10 = 2.0f * (qx * qy + qw * qz), r11 = 1.0f - 2.0f * (qx * qx + qz * qz), r12 = 2.0f * (qy * qz - qw * qx);
     const float r20 = 2.0f * (qx * qz - qw * qy), r21 = 2.0f * (qy * qz + qw * qx), r22 = 1.0f - 2.0f * (qx * qx + qy * qy);
-    const float tx = s.trans[3 * it], ty = s.trans[3 * it + 1], tz = s.trans[3 * it + 2];
-
-    float cx[2], cy[2], cz[2];
-    float eg = 0.0f;
+    const float tx = fmaf(s.trans[3 * it], g.inv_h, -g.ox_h);
+    const float ty = fmaf(s.trans[3 * it + 1], g.inv_h, -g.oy_h);
+    const float tz = fmaf(s.trans[3 * it + 2], g.inv_h, -g.oz_h);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int i = lane + kWave * h;
         cx[h] = cy[h] = cz[h] = 0.0f;
-        if (i < n) {
+        if (i < L.n) {
             const float x = L.xr[i], y = L.yr[i], z = L.zr[i];
             cx[h] = fmaf(r00, x, fmaf(r01, y, fmaf(r02, z, tx)));
             cy[h] = fmaf(r10, x, fmaf(r11, y, fmaf(r12, z, ty)));
             cz[h] = fmaf(r20, x, fmaf(r21, y, fmaf(r22, z, tz)));
-            eg += lookup<BOUNDARY>(g, L.tof[i], cx[h], cy[h], cz[h]);
         }
     }
+}
+
+// Axis of torsion k from the current coordinates: the a end and the unit direction a -> b.
+__device__ __forceinline__ void axis(const TorRec &tr, const float (&cx)[2], const float (&cy)[2], const float (&cz)[2],
+                                     float &xax, float &xay, float &xaz, float &ux, float &uy, float &uz) {
+    const int a = tr.a, b = tr.b;
+    xax = shfl_f(a < kWave ? cx[0] : cx[1], a & 63);
+    xay = shfl_f(a < kWave ? cy[0] : cy[1], a & 63);
+    xaz = shfl_f(a < kWave ? cz[0] : cz[1], a & 63);
+    const float xbx = shfl_f(b < kWave ? cx[0] : cx[1], b & 63);
+    const float xby = shfl_f(b < kWave ? cy[0] : cy[1], b & 63);
+    const float xbz = shfl_f(b < kWave ? cz[0] : cz[1], b & 63);
+    ux = xbx - xax;
+    uy = xby - xay;
+    uz = xbz - xaz;
+    const float un = 1.0f / sqrtf(fmaf(ux, ux, fmaf(uy, uy, uz * uz)));
+    ux *= un;
+    uy *= un;
+    uz *= un;
+}
+
+// Score of the conformer in registers from scratch: every atom's grid term and every clash pair.
+template <int BOUNDARY>
+__device__ float direct_score(const GridC &g, rsrc_t rs, const SearchC &s, const LigLDS &L, const float (&cx)[2],
+                              const float (&cy)[2], const float (&cz)[2]) {
+    const int lane = lane_id();
+    const int n = L.n;
+    float acc = 0.0f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = lane + kWave * h;
+        if (i < n) acc += lookup_lane<BOUNDARY>(g, rs, L.tof[i], cx[h], cy[h], cz[h]);
+    }
+    for (int i = 0; i < n; ++i) {
+        const float xi = __shfl(i < kWave ? cx[0] : cx[1], i & 63);
+        const float yi = __shfl(i < kWave ? cy[0] : cy[1], i & 63);
+        const float zi = __shfl(i < kWave ? cz[0] : cz[1], i & 63);
+        const uint4 ex = L.excl[i];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = lane + kWave * h;
+            if (j > i && j < n && !mask_has(ex, j)) {
+                const float dx = cx[h] - xi, dy = cy[h] - yi, dz = cz[h] - zi;
+                const float d = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+                const float t = fmaxf(s.cut - d, 0.0f);
+                acc = fmaf(s.w * t, t, acc);
+            }
+        }
+    }
+    return wave_sum(acc);
+}
+
+// One greedy pass from rigid start p.  Returns the final score (identical on all lanes);
+// lane k (< B) receives the step chosen for torsion k in `my_step`.
+template <int APL, int BOUNDARY>
+__device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const LigLDS &L, WaveLDS &W, int p,
+                           float clash_ref, const float (&cs)[APL], const float (&sn)[APL], int &my_step) {
+    const int lane = lane_id();
+    const int n = L.n;
+    float cx[2], cy[2], cz[2];
+    place(g, s, L, p, cx, cy, cz);
+    float eg = 0.0f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = lane + kWave * h;
+        if (i < n) eg += lookup_lane<BOUNDARY>(g, rs, L.tof[i], cx[h], cy[h], cz[h]);
+    }
     float E = wave_sum(eg) + clash_ref;
+    // The score is carried incrementally in FP32; when it passed through values much larger than
+    // the final one (atoms far outside the box or clashing in the rigid pose), the cancellation
+    // would cost accuracy, so the final conformer is then rescored from scratch.
+    float Emax = fabsf(E);
+
+    // lookups are grouped four at a time: NJ angles of NA moving atoms
+    constexpr int NJ = APL < 4 ? APL : 4;
+    constexpr int NA = 4 / NJ;
+    const float edge = 1e-3f;  // margin of the inside-the-box test, in grid units
 
     for (int k = 0; k < L.B; ++k) {
         const TorRec tr = L.tor[k];
         const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
-        const int a = tr.a, b = tr.b;
-        const float xax = shfl_f(a < kWave ? cx[0] : cx[1], a & 63);
-        const float xay = shfl_f(a < kWave ? cy[0] : cy[1], a & 63);
-        const float xaz = shfl_f(a < kWave ? cz[0] : cz[1], a & 63);
-        const float xbx = shfl_f(b < kWave ? cx[0] : cx[1], b & 63);
-        const float xby = shfl_f(b < kWave ? cy[0] : cy[1], b & 63);
-        const float xbz = shfl_f(b < kWave ? cz[0] : cz[1], b & 63);
-        float ux = xbx - xax, uy = xby - xay, uz = xbz - xaz;
-        const float un = 1.0f / sqrtf(fmaf(ux, ux, fmaf(uy, uy, uz * uz)));
-        ux *= un; uy *= un; uz *= un;
+        float xax, xay, xaz, ux, uy, uz;
+        axis(tr, cx, cy, cz, xax, xay, xaz, ux, uy, uz);
 
         float e[APL];
 #pragma unroll
@@ -252,7 +385,7 @@ __device__ float run_start(const GridC &g, const SearchC &s, const LigLDS &L, Wa
 #pragma unroll
                 for (int j = 0; j < APL; ++j) {
                     const float d2 = fmaxf(fmaf(acd.y, cs[j], fmaf(acd.z, sn[j], acd.x)), 0.0f);
-                    const float t = fmaxf(s.cut - sqrtf(d2), 0.0f);
+                    const float t = fmaxf(s.cut - __builtin_amdgcn_sqrtf(d2), 0.0f);
                     e[j] = fmaf(s.w * t, t, e[j]);
                 }
             }
@@ -269,23 +402,67 @@ __device__ float run_start(const GridC &g, const SearchC &s, const LigLDS &L, Wa
                 Coef c;
                 circle(ux, uy, uz, xax, xay, xaz, cx[h], cy[h], cz[h], c.px, c.py, c.pz, c.ax, c.ay, c.az, c.bx, c.by,
                        c.bz);
-                c.tof = L.tof[i];
-                c.rho = sqrtf(fmaf(c.ax, c.ax, fmaf(c.ay, c.ay, c.az * c.az)));
+                c.rho = __builtin_amdgcn_sqrtf(fmaf(c.ax, c.ax, fmaf(c.ay, c.ay, c.az * c.az)));
                 c.zz = fmaf(ux, cx[h] - xax, fmaf(uy, cy[h] - xay, uz * (cz[h] - xaz)));
+                const bool inside = c.px - c.rho >= edge && c.py - c.rho >= edge && c.pz - c.rho >= edge &&
+                                    c.px + c.rho <= g.mx - edge && c.py + c.rho <= g.my - edge &&
+                                    c.pz + c.rho <= g.mz - edge;
+                c.tof = L.tof[i] | (inside ? kInside : 0u);
                 const int slot = lanes_below(bal);
                 W.coef[slot] = c;
                 W.atom[slot] = (uint8_t)i;
             }
             wave_sync();
             // grid terms of the moving atoms on their circles
-            for (int q = 0; q < cnt; ++q) {
-                const Coef c = W.coef[q];
+            for (int q0 = 0; q0 < cnt; q0 += NA) {
+                Coef c[NA];
+                uint32_t sof[NA];
+                bool all_inside = true;
 #pragma unroll
-                for (int j = 0; j < APL; ++j) {
-                    const float x = fmaf(c.ax, cs[j], fmaf(c.bx, sn[j], c.px));
-                    const float y = fmaf(c.ay, cs[j], fmaf(c.by, sn[j], c.py));
-                    const float z = fmaf(c.az, cs[j], fmaf(c.bz, sn[j], c.pz));
-                    e[j] += lookup<BOUNDARY>(g, c.tof, x, y, z);
+                for (int a = 0; a < NA; ++a) {
+                    c[a] = W.coef[min(q0 + a, cnt - 1)];
+                    const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)c[a].tof);
+                    sof[a] = t & ~kInside;
+                    all_inside = all_inside && (t & kInside);
+                }
+#pragma unroll
+                for (int j0 = 0; j0 < APL; j0 += NJ) {
+                    float gx[4], gy[4], gz[4], v[4];
+                    uint32_t so[4];
+#pragma unroll
+                    for (int a = 0; a < NA; ++a)
+#pragma unroll
+                        for (int jj = 0; jj < NJ; ++jj) {
+                            const int idx = a * NJ + jj, j = j0 + jj;
+                            gx[idx] = fmaf(c[a].ax, cs[j], fmaf(c[a].bx, sn[j], c[a].px));
+                            gy[idx] = fmaf(c[a].ay, cs[j], fmaf(c[a].by, sn[j], c[a].py));
+                            gz[idx] = fmaf(c[a].az, cs[j], fmaf(c[a].bz, sn[j], c[a].pz));
+                            so[idx] = sof[a];
+                        }
+                    if constexpr (BOUNDARY == DOCK_BOUNDARY_CLAMP) {
+                        if (all_inside) {
+                            lookup_group<4, true>(g, rs, so, gx, gy, gz, v);
+                        } else {  // the clamp path needs more registers: two groups of two
+#pragma unroll
+                            for (int hh = 0; hh < 4; hh += 2) {
+                                const uint32_t so2[2] = {so[hh], so[hh + 1]};
+                                const float gx2[2] = {gx[hh], gx[hh + 1]}, gy2[2] = {gy[hh], gy[hh + 1]},
+                                            gz2[2] = {gz[hh], gz[hh + 1]};
+                                float v2[2];
+                                lookup_group<2, false>(g, rs, so2, gx2, gy2, gz2, v2);
+                                v[hh] = v2[0];
+                                v[hh + 1] = v2[1];
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int idx = 0; idx < 4; ++idx) v[idx] = lookup_lane<BOUNDARY>(g, rs, so[idx], gx[idx], gy[idx], gz[idx]);
+                    }
+#pragma unroll
+                    for (int a = 0; a < NA; ++a)
+                        if (q0 + a < cnt)
+#pragma unroll
+                            for (int jj = 0; jj < NJ; ++jj) e[j0 + jj] += v[a * NJ + jj];
                 }
             }
             // (moving, fixed) clash pairs that can come within the cut-off somewhere on the circle
@@ -302,7 +479,7 @@ __device__ float run_start(const GridC &g, const SearchC &s, const LigLDS &L, Wa
                         const float vx = cx[h2] - xax, vy = cy[h2] - xay, vz = cz[h2] - xaz;
                         const float zj = fmaf(ux, vx, fmaf(uy, vy, uz * vz));
                         const float ox = fmaf(-zj, ux, vx), oy = fmaf(-zj, uy, vy), oz = fmaf(-zj, uz, vz);
-                        const float rj = sqrtf(fmaf(ox, ox, fmaf(oy, oy, oz * oz)));
+                        const float rj = __builtin_amdgcn_sqrtf(fmaf(ox, ox, fmaf(oy, oy, oz * oz)));
                         const float dr = c.rho - rj, dz = c.zz - zj;
                         keep = fmaf(dr, dr, dz * dz) < s.cut2_keep;
                         const float wx = c.px - cx[h2], wy = c.py - cy[h2], wz = c.pz - cz[h2];
@@ -344,6 +521,7 @@ __device__ float run_start(const GridC &g, const SearchC &s, const LigLDS &L, Wa
         const float ebest = ordered_to_float((uint32_t)(best >> 32));
         const float e0 = __shfl(e[0], 0);
         E += ebest - e0;
+        Emax = fmaxf(Emax, fabsf(E));
 
         // apply the winning step
         const int jb = sbest / kWave, owner = sbest - jb * kWave;
@@ -368,6 +546,7 @@ __device__ float run_start(const GridC &g, const SearchC &s, const LigLDS &L, Wa
         }
         if (lane == k) my_step = sbest;
     }
+    if (Emax > 16.0f * fmaxf(1.0f, fabsf(E))) E = direct_score<BOUNDARY>(g, rs, s, L, cx, cy, cz);
     return E;
 }
 
@@ -383,6 +562,7 @@ struct ScreenArgs {
     uint64_t *best_key;      // [n_lig]
     uint32_t *counter;
     float *start_scores;     // optional [n_lig][QT]
+    uint16_t *start_steps;   // optional [n_lig][QT][16]
     int n_lig, P, bpl, nw;
     int64_t n_items;
 };
@@ -421,7 +601,7 @@ __global__ void k_screen_plan(const LigDesc *desc, int n_lig, int S, uint64_t *k
 }
 
 template <int APL, int BOUNDARY>
-__global__ __launch_bounds__(512) void k_screen(ScreenArgs A) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_screen(ScreenArgs A) {
     extern __shared__ __align__(16) char smem[];
     LigLDS &L = *reinterpret_cast<LigLDS *>(smem);
     WaveLDS *Wv = reinterpret_cast<WaveLDS *>(smem + ((sizeof(LigLDS) + 15) & ~size_t(15)));
@@ -431,6 +611,7 @@ __global__ __launch_bounds__(512) void k_screen(ScreenArgs A) {
     WaveLDS &W = Wv[w];
     float cs[APL], sn[APL];
     angle_table<APL>(A.s.S, cs, sn);
+    const rsrc_t rs = grid_rsrc(A.g);
 
     for (;;) {
         if (tid == 0) item_s = (int)atomicAdd(A.counter, 1u);
@@ -439,7 +620,7 @@ __global__ __launch_bounds__(512) void k_screen(ScreenArgs A) {
         if (item >= A.n_items) break;
         const int slot = (int)(item / A.bpl), batch = (int)(item - (int64_t)slot * A.bpl);
         const int lig = (int)(uint32_t)A.order[slot];
-        load_ligand(L, A.pk, lig, A.g.nxyz, tid, blockDim.x);
+        load_ligand(L, A.pk, lig, A.g, tid, blockDim.x);
         __syncthreads();
         if (L.status == DOCK_LIG_OK) {
             const float clash_ref = rigid_clash(L, A.s);
@@ -447,10 +628,13 @@ __global__ __launch_bounds__(512) void k_screen(ScreenArgs A) {
             const int p0 = batch * A.P, p1 = min(p0 + A.P, A.s.QT);
             for (int p = p0 + w; p < p1; p += A.nw) {
                 int step = 0;
-                const float E = run_start<APL, BOUNDARY>(A.g, A.s, L, W, p, clash_ref, cs, sn, step);
+                const float E = run_start<APL, BOUNDARY>(A.g, rs, A.s, L, W, p, clash_ref, cs, sn, step);
                 const uint64_t key = ((uint64_t)float_to_ordered(E) << 32) | (uint32_t)p;
                 wbest = key < wbest ? key : wbest;
                 if (A.start_scores && lane == 0) A.start_scores[(size_t)lig * A.s.QT + p] = E;
+                if (A.start_steps && lane < DOCK_MAX_TORSIONS)
+                    A.start_steps[((size_t)lig * A.s.QT + p) * DOCK_MAX_TORSIONS + lane] =
+                        (uint16_t)(lane < L.B ? step : 0);
             }
             if (lane == 0) wbest_s[w] = wbest;
         }
@@ -474,7 +658,8 @@ __global__ __launch_bounds__(64) void k_replay(ScreenArgs A, float *best_score, 
     const int lig = blockIdx.x, lane = lane_id();
     float cs[APL], sn[APL];
     angle_table<APL>(A.s.S, cs, sn);
-    load_ligand(L, A.pk, lig, A.g.nxyz, lane, kWave);
+    const rsrc_t rs = grid_rsrc(A.g);
+    load_ligand(L, A.pk, lig, A.g, lane, kWave);
     __syncthreads();
     const uint64_t key = A.best_key[lig];
     int step = 0;
@@ -483,7 +668,7 @@ __global__ __launch_bounds__(64) void k_replay(ScreenArgs A, float *best_score, 
     if (L.status == DOCK_LIG_OK && key != ~0ull) {
         p = (int)(uint32_t)key;
         const float clash_ref = rigid_clash(L, A.s);
-        E = run_start<APL, BOUNDARY>(A.g, A.s, L, W, p, clash_ref, cs, sn, step);
+        E = run_start<APL, BOUNDARY>(A.g, rs, A.s, L, W, p, clash_ref, cs, sn, step);
     }
     if (lane < DOCK_MAX_TORSIONS) best_steps[(size_t)lig * DOCK_MAX_TORSIONS + lane] =
         (uint16_t)(p >= 0 && lane < L.B ? step : 0);
@@ -507,46 +692,21 @@ __global__ __launch_bounds__(64) void k_score_poses(GridC g, SearchC s, PackView
         if (lane == 0) out[pose] = NAN;
         return;
     }
-    load_ligand(L, pk, lig, g.nxyz, lane, kWave);
+    load_ligand(L, pk, lig, g, lane, kWave);
     __syncthreads();
     if (L.status != DOCK_LIG_OK) {
         if (lane == 0) out[pose] = INFINITY;
         return;
     }
+    const rsrc_t rs = grid_rsrc(g);
     const int n = L.n;
-    const int iq = p / s.n_trans, it = p - iq * s.n_trans;
-    float qw = s.quat[4 * iq], qx = s.quat[4 * iq + 1], qy = s.quat[4 * iq + 2], qz = s.quat[4 * iq + 3];
-    const float qn = 1.0f / sqrtf(fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz))));
-    qw *= qn; qx *= qn; qy *= qn; qz *= qn;
-    const float r00 = 1.0f - 2.0f * (qy * qy + qz * qz), r01 = 2.0f * (qx * qy - qw * qz), r02 = 2.0f * (qx * qz + qw * qy);
-    const float r10 = 2.0f * (qx * qy + qw * qz), r11 = 1.0f - 2.0f * (qx * qx + qz * qz), r12 = 2.0f * (qy * qz - qw * qx);
-    const float r20 = 2.0f * (qx * qz - qw * qy), r21 = 2.0f * (qy * qz + qw * qx), r22 = 1.0f - 2.0f * (qx * qx + qy * qy);
-    const float tx = s.trans[3 * it], ty = s.trans[3 * it + 1], tz = s.trans[3 * it + 2];
     float cx[2], cy[2], cz[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int i = lane + kWave * h;
-        cx[h] = cy[h] = cz[h] = 0.0f;
-        if (i < n) {
-            const float x = L.xr[i], y = L.yr[i], z = L.zr[i];
-            cx[h] = fmaf(r00, x, fmaf(r01, y, fmaf(r02, z, tx)));
-            cy[h] = fmaf(r10, x, fmaf(r11, y, fmaf(r12, z, ty)));
-            cz[h] = fmaf(r20, x, fmaf(r21, y, fmaf(r22, z, tz)));
-        }
-    }
+    place(g, s, L, p, cx, cy, cz);
     for (int k = 0; k < L.B; ++k) {
         const TorRec tr = L.tor[k];
         const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
-        const int a = tr.a, b = tr.b;
-        const float xax = __shfl(a < kWave ? cx[0] : cx[1], a & 63);
-        const float xay = __shfl(a < kWave ? cy[0] : cy[1], a & 63);
-        const float xaz = __shfl(a < kWave ? cz[0] : cz[1], a & 63);
-        const float xbx = __shfl(b < kWave ? cx[0] : cx[1], b & 63);
-        const float xby = __shfl(b < kWave ? cy[0] : cy[1], b & 63);
-        const float xbz = __shfl(b < kWave ? cz[0] : cz[1], b & 63);
-        float ux = xbx - xax, uy = xby - xay, uz = xbz - xaz;
-        const float un = 1.0f / sqrtf(fmaf(ux, ux, fmaf(uy, uy, uz * uz)));
-        ux *= un; uy *= un; uz *= un;
+        float xax, xay, xaz, ux, uy, uz;
+        axis(tr, cx, cy, cz, xax, xay, xaz, ux, uy, uz);
         const int st = d_steps[pose * DOCK_MAX_TORSIONS + k];
         float sb, cb;
         sincospif(2.0f * (float)st / (float)s.S, &sb, &cb);
@@ -562,29 +722,8 @@ __global__ __launch_bounds__(64) void k_score_poses(GridC g, SearchC s, PackView
             }
         }
     }
-    float acc = 0.0f;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int i = lane + kWave * h;
-        if (i < n) acc += lookup<BOUNDARY>(g, L.tof[i], cx[h], cy[h], cz[h]);
-    }
-    for (int i = 0; i < n; ++i) {
-        const float xi = __shfl(i < kWave ? cx[0] : cx[1], i & 63);
-        const float yi = __shfl(i < kWave ? cy[0] : cy[1], i & 63);
-        const float zi = __shfl(i < kWave ? cz[0] : cz[1], i & 63);
-        const uint4 ex = L.excl[i];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int j = lane + kWave * h;
-            if (j > i && j < n && !mask_has(ex, j)) {
-                const float dx = cx[h] - xi, dy = cy[h] - yi, dz = cz[h] - zi;
-                const float d = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-                const float t = fmaxf(s.cut - d, 0.0f);
-                acc = fmaf(s.w * t, t, acc);
-            }
-        }
-    }
-    acc = wave_sum(acc);
+    // every atom's grid term and every clash pair, from the final coordinates
+    const float acc = direct_score<BOUNDARY>(g, rs, s, L, cx, cy, cz);
     if (lane == 0) out[pose] = acc;
 }
 
@@ -598,8 +737,11 @@ static GridC make_grid(const dock_grid_desc *d, const float *G) {
     g.nx = d->nx;
     g.ny = d->ny;
     g.nz = d->nz;
-    g.nxy = d->nx * d->ny;
-    g.nxyz = d->nx * d->ny * d->nz;
+    g.total_bytes = 4u * (uint32_t)d->n_types * (uint32_t)(d->nx * d->ny * d->nz);
+    g.nx4 = 4u * (uint32_t)d->nx;
+    g.nxy4 = 4u * (uint32_t)(d->nx * d->ny);
+    g.fnx4 = (float)g.nx4;
+    g.fnxy4 = (float)g.nxy4;
     g.inv_h = 1.0f / d->spacing;
     g.ox_h = d->origin[0] / d->spacing;
     g.oy_h = d->origin[1] / d->spacing;
@@ -626,7 +768,7 @@ static int check_search(const dock_search *s) {
     return DOCK_OK;
 }
 
-static SearchC make_search(const dock_search *d) {
+static SearchC make_search(const dock_search *d, float spacing) {
     SearchC s;
     s.quat = d->d_quat;
     s.trans = d->d_trans;
@@ -634,10 +776,10 @@ static SearchC make_search(const dock_search *d) {
     s.n_trans = d->n_trans;
     s.S = d->n_steps;
     s.QT = d->n_quat * d->n_trans;
-    s.cut = d->clash_cut;
-    const float keep = d->clash_cut + 1e-3f;
+    s.cut = d->clash_cut / spacing;
+    const float keep = s.cut + 1e-3f;  // pairs this close somewhere on the circle are kept
     s.cut2_keep = keep * keep;
-    s.w = d->clash_w;
+    s.w = d->clash_w * spacing * spacing;
     return s;
 }
 
@@ -689,7 +831,8 @@ using namespace ligate;
 
 extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const void *d_pack, int32_t n_lig,
                            int64_t n_atoms_total, const dock_search *sd, float *d_best_score, int32_t *d_best_start,
-                           uint16_t *d_best_steps, float *d_start_scores, uint64_t *d_pose_count, void *d_ws,
+                           uint16_t *d_best_steps, float *d_start_scores, uint16_t *d_start_steps,
+                           uint64_t *d_pose_count, void *d_ws,
                            size_t *ws_bytes, void *stream) {
     int rc = grid_desc_check(gd);
     if (rc) return rc;
@@ -716,12 +859,13 @@ extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const
     ScreenArgs A;
     A.g = make_grid(gd, d_grids);
     A.g.G = d_grids;
-    A.s = make_search(sd);
+    A.s = make_search(sd, gd->spacing);
     A.pk = PackView::of(d_pack, n_lig, n_atoms_total);
     A.order = order;
     A.best_key = best_key;
     A.counter = counter;
     A.start_scores = d_start_scores;
+    A.start_steps = d_start_steps;
     A.n_lig = n_lig;
     A.nw = sd->waves_per_block ? sd->waves_per_block : 4;
     LIGATE_REQUIRE(A.nw == 1 || A.nw == 2 || A.nw == 4 || A.nw == 8, DOCK_ERR_INVALID_ARG,
@@ -763,7 +907,7 @@ extern "C" int dock_score_poses(const dock_grid_desc *gd, const float *d_grids, 
     if (n_poses == 0) return DOCK_OK;
     LIGATE_REQUIRE(d_grids && d_pack && d_lig && d_start && d_steps && d_scores, DOCK_ERR_INVALID_ARG, "NULL array");
     const GridC g = make_grid(gd, d_grids);
-    const SearchC s = make_search(sd);
+    const SearchC s = make_search(sd, gd->spacing);
     const PackView pk = PackView::of(d_pack, n_lig, n_atoms_total);
     hipStream_t st = (hipStream_t)stream;
     if (gd->boundary == DOCK_BOUNDARY_PERIODIC)

@@ -1,0 +1,534 @@
+// Learned pre-filter: ligand features, a 3-layer MLP on the matrix cores (BF16 operands, FP32
+// accumulation, v_mfma_f32_32x32x16_bf16), its backward pass and Adam.
+#include <math.h>
+
+#include <algorithm>
+
+#include "common.h"
+#include "ligate_surrogate.h"
+
+namespace ligate {
+
+// ---------------------------------------------------------------------------------------------
+// BF16 helpers (round to nearest even)
+// ---------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// ---------------------------------------------------------------------------------------------
+// Features: one wavefront per ligand
+// ---------------------------------------------------------------------------------------------
+
+constexpr int kRows = 16, kSlots = 32, kBins = 30;
+
+__global__ __launch_bounds__(64) void k_features(const int32_t *__restrict__ atom_off, const float *__restrict__ xyz,
+                                                 const uint8_t *__restrict__ type, PackView pk,
+                                                 const float *__restrict__ mean, const float *__restrict__ istd,
+                                                 float *__restrict__ out_f, uint16_t *__restrict__ out_b) {
+    __shared__ int cnt[kRows * kSlots];
+    const int l = blockIdx.x, lane = lane_id();
+    const LigDesc d = pk.desc[l];
+    const bool ok = d.status == DOCK_LIG_OK;
+    for (int f = lane; f < kRows * kSlots; f += kWave) cnt[f] = 0;
+    wave_sync();
+    if (ok) {
+        const int a0 = atom_off[l], n = d.n;
+        for (int i = lane; i < n; i += kWave) {
+            const int ti = type[a0 + i];
+            atomicAdd(&cnt[ti * kSlots], 1);
+            const float xi = xyz[3 * (a0 + i)], yi = xyz[3 * (a0 + i) + 1], zi = xyz[3 * (a0 + i) + 2];
+            for (int j = 0; j < n; ++j) {
+                if (j == i) continue;
+                // squared distance with every product and sum rounded (no contraction), so the
+                // bin decision is reproducible
+                const float dx = __fsub_rn(xi, xyz[3 * (a0 + j)]);
+                const float dy = __fsub_rn(yi, xyz[3 * (a0 + j) + 1]);
+                const float dz = __fsub_rn(zi, xyz[3 * (a0 + j) + 2]);
+                const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+                // first guess from the distance, then exact comparisons with the squared edges
+                // 1.25 + 0.5 k (k = 1..29), which are representable exactly
+                int b = (int)((sqrtf(d2) - 1.25f) * 2.0f);
+                b = b < 0 ? 0 : (b > kBins - 1 ? kBins - 1 : b);
+                while (b < kBins - 1) {
+                    const float e = 1.25f + 0.5f * (float)(b + 1);
+                    if (d2 >= e * e) ++b; else break;
+                }
+                while (b > 0) {
+                    const float e = 1.25f + 0.5f * (float)b;
+                    if (d2 < e * e) --b; else break;
+                }
+                atomicAdd(&cnt[ti * kSlots + 1 + b], 1);
+            }
+        }
+    }
+    wave_sync();
+    for (int f = lane; f < kRows * kSlots; f += kWave) {
+        float v = 0.0f;
+        if (ok) {
+            const int c = (f % kSlots == kSlots - 1) ? d.B : cnt[f];
+            v = log1pf((float)c);
+            if (mean) v = (v - mean[f]) * istd[f];
+        }
+        if (out_f) out_f[(size_t)l * SURR_FEATURES + f] = v;
+        if (out_b) out_b[(size_t)l * SURR_FEATURES + f] = f2bf(v);
+    }
+}
+
+// Column statistics: FP64 partial sums per (chunk of rows, column), then a fixed-order total.
+constexpr int kStatRows = 1024;
+
+__global__ __launch_bounds__(64) void k_stats_partial(const float *__restrict__ F, int64_t n_rows,
+                                                      double *__restrict__ part) {
+    const int col = blockIdx.y * kWave + threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kStatRows, r1 = min(n_rows, r0 + kStatRows);
+    double s = 0.0, q = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const double v = F[r * SURR_FEATURES + col];
+        s += v;
+        q += v * v;
+    }
+    part[((int64_t)blockIdx.x * SURR_FEATURES + col) * 2] = s;
+    part[((int64_t)blockIdx.x * SURR_FEATURES + col) * 2 + 1] = q;
+}
+
+__global__ void k_stats_final(const double *__restrict__ part, int n_chunks, int64_t n_rows, float *mean,
+                              float *istd) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= SURR_FEATURES) return;
+    double s = 0.0, q = 0.0;
+    for (int c = 0; c < n_chunks; ++c) {
+        s += part[((int64_t)c * SURR_FEATURES + col) * 2];
+        q += part[((int64_t)c * SURR_FEATURES + col) * 2 + 1];
+    }
+    const double m = s / (double)n_rows;
+    const double var = fmax(q / (double)n_rows - m * m, 0.0);
+    const double sd = sqrt(var);
+    mean[col] = (float)m;
+    istd[col] = sd < 1e-6 ? 1.0f : (float)(1.0 / sd);  // constant features are left unscaled
+}
+
+// ---------------------------------------------------------------------------------------------
+// GEMM on the matrix cores: C = A B, BF16 operands, FP32 accumulation.
+// A (m, k) is at A[m * lda + k] (A_K) or A[k * lda + m]; B (k, n) at B[n * ldb + k] (B_K) or
+// B[k * ldb + n].  N is a multiple of 64 and K of 32; rows m >= M are skipped.
+// Tiles of 64 x 64 per block of four wavefronts, each wavefront a 32 x 32 MFMA tile.
+// ---------------------------------------------------------------------------------------------
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+enum { EPI_F32 = 0, EPI_BIAS_RELU_BF16 = 1, EPI_MASK_BF16 = 2 };
+
+constexpr int kBM = 64, kBN = 64, kBK = 32, kPitch = kBK + 8;  // LDS rows padded against bank conflicts
+
+template <bool A_K, bool B_K, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
+                                              const uint16_t *__restrict__ B, int ldb, float *__restrict__ Cf,
+                                              uint16_t *__restrict__ Cb, int ldc, const float *__restrict__ bias,
+                                              const uint16_t *__restrict__ mask, int ldm) {
+    __shared__ __align__(16) uint16_t As[kBM * kPitch];
+    __shared__ __align__(16) uint16_t Bs[kBN * kPitch];
+    const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+    const int wm = w >> 1, wn = w & 1;
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+
+    for (int k0 = 0; k0 < K; k0 += kBK) {
+        // stage A and B tiles, K contiguous per row
+        if constexpr (A_K) {
+            const int r = t >> 2, c = (t & 3) * 8;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (m0 + r < M) v = *reinterpret_cast<const uint4 *>(A + (size_t)(m0 + r) * lda + k0 + c);
+            *reinterpret_cast<uint4 *>(As + r * kPitch + c) = v;
+        } else {
+            const int kk = t >> 3, mm = (t & 7) * 8;
+            uint16_t v[8];
+            if (m0 + mm + 8 <= M) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(A + (size_t)(k0 + kk) * lda + m0 + mm);
+                __builtin_memcpy(v, &q, 16);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = m0 + mm + i < M ? A[(size_t)(k0 + kk) * lda + m0 + mm + i] : 0;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) As[(mm + i) * kPitch + kk] = v[i];
+        }
+        if constexpr (B_K) {
+            const int r = t >> 2, c = (t & 3) * 8;
+            *reinterpret_cast<uint4 *>(Bs + r * kPitch + c) =
+                *reinterpret_cast<const uint4 *>(B + (size_t)(n0 + r) * ldb + k0 + c);
+        } else {
+            const int kk = t >> 3, nn = (t & 7) * 8;
+            const uint4 q = *reinterpret_cast<const uint4 *>(B + (size_t)(k0 + kk) * ldb + n0 + nn);
+            uint16_t v[8];
+            __builtin_memcpy(v, &q, 16);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[(nn + i) * kPitch + kk] = v[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kBK; kk += 16) {
+            const int kq = kk + 8 * (lane >> 5);
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(As + (wm * 32 + (lane & 31)) * kPitch + kq);
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bs + (wn * 32 + (lane & 31)) * kPitch + kq);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // lane holds column (lane & 31) of rows 8 (r / 4) + 4 (lane / 32) + r % 4 of its 32 x 32 tile
+    const int col = n0 + wn * 32 + (lane & 31);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row >= M) continue;
+        const float v = acc[r];
+        if constexpr (EPI == EPI_F32) {
+            Cf[(size_t)row * ldc + col] = v;
+        } else if constexpr (EPI == EPI_BIAS_RELU_BF16) {
+            Cb[(size_t)row * ldc + col] = f2bf(fmaxf(v + bias[col], 0.0f));
+        } else {
+            Cb[(size_t)row * ldc + col] = bf2f(mask[(size_t)row * ldm + col]) > 0.0f ? f2bf(v) : (uint16_t)0;
+        }
+    }
+}
+
+template <bool A_K, bool B_K, int EPI>
+static void gemm(hipStream_t st, int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B, int ldb,
+                 float *Cf, uint16_t *Cb, int ldc, const float *bias = nullptr, const uint16_t *mask = nullptr,
+                 int ldm = 0) {
+    dim3 grid((unsigned)(N / kBN), (unsigned)((M + kBM - 1) / kBM));
+    hipLaunchKernelGGL((k_gemm<A_K, B_K, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, Cf, Cb, ldc, bias,
+                       mask, ldm);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Output layer, loss, reductions, Adam
+// ---------------------------------------------------------------------------------------------
+
+// y[b] = sum_k H2[b][k] w3[k] + b3; with targets also r2[b] = (y - t)^2 and dy[b] = 2 (y - t) / B.
+__global__ __launch_bounds__(64) void k_head(const uint16_t *__restrict__ H2, int h2, const uint16_t *__restrict__ w3,
+                                             const float *__restrict__ b3, int batch, float *__restrict__ y,
+                                             const float *__restrict__ target, float *__restrict__ r2,
+                                             float *__restrict__ dy) {
+    const int b = blockIdx.x, lane = lane_id();
+    float acc = 0.0f;
+    for (int k = lane; k < h2; k += kWave) acc = fmaf(bf2f(H2[(size_t)b * h2 + k]), bf2f(w3[k]), acc);
+    const float v = wave_sum(acc) + b3[0];
+    if (lane == 0) {
+        if (y) y[b] = v;
+        if (target) {
+            const float e = v - target[b];
+            r2[b] = e * e;
+            dy[b] = 2.0f * e / (float)batch;
+        }
+    }
+}
+
+// loss = sum r2 / B and db3 = sum dy, in a fixed order (one wavefront).
+__global__ __launch_bounds__(64) void k_loss(const float *__restrict__ r2, const float *__restrict__ dy, int batch,
+                                             float *loss, float *db3) {
+    const int lane = lane_id();
+    float s = 0.0f, g = 0.0f;
+    for (int b = lane; b < batch; b += kWave) {
+        s += r2[b];
+        g += dy[b];
+    }
+    s = wave_sum(s);
+    g = wave_sum(g);
+    if (lane == 0) {
+        *loss = s / (float)batch;
+        *db3 = g;
+    }
+}
+
+// dH2[b][k] = dy[b] w3[k] where H2[b][k] > 0, stored in BF16.
+__global__ void k_head_back(const uint16_t *__restrict__ H2, const uint16_t *__restrict__ w3,
+                            const float *__restrict__ dy, int batch, int h2, uint16_t *__restrict__ dH2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)batch * h2) return;
+    const int b = (int)(i / h2), k = (int)(i - (int64_t)b * h2);
+    dH2[i] = bf2f(H2[i]) > 0.0f ? f2bf(dy[b] * bf2f(w3[k])) : (uint16_t)0;
+}
+
+// out[c] = sum_r wgt[r] X[r][c] (wgt == NULL: plain sum), rows in order.
+__global__ void k_colsum(const uint16_t *__restrict__ X, int rows, int cols, const float *__restrict__ wgt,
+                         float *__restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.0f;
+    for (int r = 0; r < rows; ++r) {
+        const float v = bf2f(X[(size_t)r * cols + c]);
+        s = wgt ? fmaf(wgt[r], v, s) : s + v;
+    }
+    out[c] = s;
+}
+
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// BF16 copies of W1, W2 and w3 from the master weights.
+__global__ void k_cast(const float *__restrict__ master, uint16_t *__restrict__ out, int64_t n_w1, int64_t off_w2,
+                       int64_t n_w2, int64_t off_w3, int64_t n_w3) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_w1) out[i] = f2bf(master[i]);
+    else if (i < n_w1 + n_w2) out[i] = f2bf(master[off_w2 + (i - n_w1)]);
+    else if (i < n_w1 + n_w2 + n_w3) out[i] = f2bf(master[off_w3 + (i - n_w1 - n_w2)]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------------------------
+
+struct Layout {  // offsets into the master / BF16 arrays
+    int64_t W1, b1, W2, b2, w3, b3, n_master;
+    int64_t bW1, bW2, bw3, n_bf16;
+    static Layout of(int d, int h1, int h2) {
+        Layout L;
+        L.W1 = 0;
+        L.b1 = L.W1 + (int64_t)h1 * d;
+        L.W2 = L.b1 + h1;
+        L.b2 = L.W2 + (int64_t)h2 * h1;
+        L.w3 = L.b2 + h2;
+        L.b3 = L.w3 + h2;
+        L.n_master = L.b3 + 1;
+        L.bW1 = 0;
+        L.bW2 = (int64_t)h1 * d;
+        L.bw3 = L.bW2 + (int64_t)h2 * h1;
+        L.n_bf16 = L.bw3 + h2;
+        return L;
+    }
+};
+
+static size_t al(size_t v) { return (v + 255) & ~size_t(255); }
+
+static int check_model(const surr_model *m, bool need_train) {
+    LIGATE_REQUIRE(m != nullptr, DOCK_ERR_INVALID_ARG, "model is NULL");
+    LIGATE_REQUIRE(m->d_in > 0 && m->h1 > 0 && m->h2 > 0 && m->d_in % 64 == 0 && m->h1 % 64 == 0 && m->h2 % 64 == 0,
+                   DOCK_ERR_INVALID_ARG, "layer widths must be positive multiples of 64");
+    LIGATE_REQUIRE(m->d_master && m->d_bf16, DOCK_ERR_INVALID_ARG, "model weights are NULL");
+    if (need_train)
+        LIGATE_REQUIRE(m->d_grad && m->d_adam_m && m->d_adam_v, DOCK_ERR_INVALID_ARG, "training buffers are NULL");
+    return DOCK_OK;
+}
+
+struct FwdWs {
+    uint16_t *H1, *H2;
+};
+
+static size_t fwd_ws_bytes(const surr_model *m, int batch) {
+    return al(2 * (size_t)batch * m->h1) + al(2 * (size_t)batch * m->h2);
+}
+
+static FwdWs fwd_ws(const surr_model *m, int batch, void *ws) {
+    char *p = (char *)ws;
+    FwdWs w;
+    w.H1 = (uint16_t *)p;
+    w.H2 = (uint16_t *)(p + al(2 * (size_t)batch * m->h1));
+    return w;
+}
+
+static void run_forward(const surr_model *m, const Layout &L, const uint16_t *x, int batch, const FwdWs &w,
+                        hipStream_t st) {
+    const uint16_t *W1 = m->d_bf16 + L.bW1, *W2 = m->d_bf16 + L.bW2;
+    gemm<true, true, EPI_BIAS_RELU_BF16>(st, batch, m->h1, m->d_in, x, m->d_in, W1, m->d_in, nullptr, w.H1, m->h1,
+                                         m->d_master + L.b1);
+    gemm<true, true, EPI_BIAS_RELU_BF16>(st, batch, m->h2, m->h1, w.H1, m->h1, W2, m->h1, nullptr, w.H2, m->h2,
+                                         m->d_master + L.b2);
+}
+
+}  // namespace ligate
+
+using namespace ligate;
+
+extern "C" int surr_param_count(int32_t d_in, int32_t h1, int32_t h2, int64_t *n_master, int64_t *n_bf16) {
+    LIGATE_REQUIRE(d_in > 0 && h1 > 0 && h2 > 0 && n_master && n_bf16, DOCK_ERR_INVALID_ARG, "bad widths");
+    const Layout L = Layout::of(d_in, h1, h2);
+    *n_master = L.n_master;
+    *n_bf16 = L.n_bf16;
+    return DOCK_OK;
+}
+
+extern "C" int surr_features(const int32_t *d_atom_off, const float *d_xyz, const uint8_t *d_type, const void *d_pack,
+                             int32_t n_lig, int64_t n_atoms_total, int32_t n_types, const float *d_mean,
+                             const float *d_istd, float *d_feat, uint16_t *d_feat_bf16, void *stream) {
+    LIGATE_REQUIRE(n_lig >= 0 && n_atoms_total >= 0 && n_atoms_total < (1ll << 31), DOCK_ERR_INVALID_ARG,
+                   "bad library size");
+    LIGATE_REQUIRE(n_types >= 1 && n_types <= SURR_MAX_TYPES, DOCK_ERR_LIMIT, "features need n_types <= 16");
+    LIGATE_REQUIRE((d_mean == nullptr) == (d_istd == nullptr), DOCK_ERR_INVALID_ARG, "mean and istd go together");
+    LIGATE_REQUIRE(d_feat || d_feat_bf16, DOCK_ERR_INVALID_ARG, "no output");
+    if (n_lig == 0) return DOCK_OK;
+    LIGATE_REQUIRE(d_atom_off && d_xyz && d_type && d_pack, DOCK_ERR_INVALID_ARG, "NULL input");
+    const PackView pk = PackView::of(d_pack, n_lig, n_atoms_total);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)n_lig), dim3(kWave), 0, (hipStream_t)stream, d_atom_off, d_xyz,
+                       d_type, pk, d_mean, d_istd, d_feat, d_feat_bf16);
+    return check_launch("surr_features");
+}
+
+extern "C" int surr_feature_stats(const float *d_feat, int64_t n_rows, float *d_mean, float *d_istd, void *d_ws,
+                                  size_t *ws_bytes, void *stream) {
+    LIGATE_REQUIRE(n_rows >= 1 && ws_bytes, DOCK_ERR_INVALID_ARG, "bad arguments");
+    const int64_t chunks = (n_rows + kStatRows - 1) / kStatRows;
+    const size_t need = al(sizeof(double) * 2 * SURR_FEATURES * (size_t)chunks);
+    if (d_ws == nullptr) {
+        *ws_bytes = need;
+        return DOCK_OK;
+    }
+    LIGATE_REQUIRE(*ws_bytes >= need, DOCK_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", *ws_bytes, need);
+    LIGATE_REQUIRE(d_feat && d_mean && d_istd, DOCK_ERR_INVALID_ARG, "NULL array");
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_stats_partial, dim3((unsigned)chunks, SURR_FEATURES / kWave), dim3(kWave), 0, st, d_feat,
+                       n_rows, (double *)d_ws);
+    hipLaunchKernelGGL(k_stats_final, dim3(SURR_FEATURES / 256), dim3(256), 0, st, (const double *)d_ws, (int)chunks,
+                       n_rows, d_mean, d_istd);
+    return check_launch("surr_feature_stats");
+}
+
+extern "C" int surr_cast(const surr_model *m, void *stream) {
+    int rc = check_model(m, false);
+    if (rc) return rc;
+    const Layout L = Layout::of(m->d_in, m->h1, m->h2);
+    const int64_t n = L.n_bf16;
+    hipLaunchKernelGGL(k_cast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, m->d_master,
+                       m->d_bf16, (int64_t)m->h1 * m->d_in, L.W2, (int64_t)m->h2 * m->h1, L.w3, (int64_t)m->h2);
+    return check_launch("surr_cast");
+}
+
+extern "C" int surr_forward(const surr_model *m, const uint16_t *d_x, int32_t batch, float *d_y, void *d_ws,
+                            size_t *ws_bytes, void *stream) {
+    int rc = check_model(m, false);
+    if (rc) return rc;
+    LIGATE_REQUIRE(batch >= 1 && ws_bytes, DOCK_ERR_INVALID_ARG, "bad batch");
+    const size_t need = fwd_ws_bytes(m, batch);
+    if (d_ws == nullptr) {
+        *ws_bytes = need;
+        return DOCK_OK;
+    }
+    LIGATE_REQUIRE(*ws_bytes >= need, DOCK_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", *ws_bytes, need);
+    LIGATE_REQUIRE(d_x && d_y, DOCK_ERR_INVALID_ARG, "NULL array");
+    hipStream_t st = (hipStream_t)stream;
+    const Layout L = Layout::of(m->d_in, m->h1, m->h2);
+    const FwdWs w = fwd_ws(m, batch, d_ws);
+    run_forward(m, L, d_x, batch, w, st);
+    hipLaunchKernelGGL(k_head, dim3((unsigned)batch), dim3(kWave), 0, st, w.H2, m->h2, m->d_bf16 + L.bw3,
+                       m->d_master + L.b3, batch, d_y, (const float *)nullptr, (float *)nullptr, (float *)nullptr);
+    return check_launch("surr_forward");
+}
+
+extern "C" int surr_backward(const surr_model *m, const uint16_t *d_x, const float *d_t, int32_t batch, float *d_loss,
+                             void *d_ws, size_t *ws_bytes, void *stream) {
+    int rc = check_model(m, true);
+    if (rc) return rc;
+    LIGATE_REQUIRE(batch >= 32 && batch % 32 == 0 && ws_bytes, DOCK_ERR_INVALID_ARG,
+                   "batch must be a positive multiple of 32");
+    const size_t f = fwd_ws_bytes(m, batch);
+    const size_t need = f + al(2 * (size_t)batch * m->h2) + al(2 * (size_t)batch * m->h1) + 2 * al(4 * (size_t)batch);
+    if (d_ws == nullptr) {
+        *ws_bytes = need;
+        return DOCK_OK;
+    }
+    LIGATE_REQUIRE(*ws_bytes >= need, DOCK_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", *ws_bytes, need);
+    LIGATE_REQUIRE(d_x && d_t && d_loss, DOCK_ERR_INVALID_ARG, "NULL array");
+    hipStream_t st = (hipStream_t)stream;
+    const Layout L = Layout::of(m->d_in, m->h1, m->h2);
+    const FwdWs w = fwd_ws(m, batch, d_ws);
+    char *p = (char *)d_ws + f;
+    uint16_t *dH2 = (uint16_t *)p;
+    p += al(2 * (size_t)batch * m->h2);
+    uint16_t *dH1 = (uint16_t *)p;
+    p += al(2 * (size_t)batch * m->h1);
+    float *dy = (float *)p;
+    p += al(4 * (size_t)batch);
+    float *r2 = (float *)p;
+    float *g = m->d_grad;
+
+    run_forward(m, L, d_x, batch, w, st);
+    hipLaunchKernelGGL(k_head, dim3((unsigned)batch), dim3(kWave), 0, st, w.H2, m->h2, m->d_bf16 + L.bw3,
+                       m->d_master + L.b3, batch, (float *)nullptr, d_t, r2, dy);
+    hipLaunchKernelGGL(k_loss, dim3(1), dim3(kWave), 0, st, r2, dy, batch, d_loss, g + L.b3);
+    // output layer
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((m->h2 + 255) / 256)), dim3(256), 0, st, w.H2, batch, m->h2, dy,
+                       g + L.w3);
+    const int64_t n2 = (int64_t)batch * m->h2;
+    hipLaunchKernelGGL(k_head_back, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, w.H2, m->d_bf16 + L.bw3, dy,
+                       batch, m->h2, dH2);
+    // second layer: dW2 = dH2^T H1, db2 = column sums of dH2, dH1 = (dH2 W2) where H1 > 0
+    gemm<false, false, EPI_F32>(st, m->h2, m->h1, batch, dH2, m->h2, w.H1, m->h1, g + L.W2, nullptr, m->h1);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((m->h2 + 255) / 256)), dim3(256), 0, st, dH2, batch, m->h2,
+                       (const float *)nullptr, g + L.b2);
+    gemm<true, false, EPI_MASK_BF16>(st, batch, m->h1, m->h2, dH2, m->h2, m->d_bf16 + L.bW2, m->h1, nullptr, dH1,
+                                     m->h1, nullptr, w.H1, m->h1);
+    // first layer: dW1 = dH1^T x, db1 = column sums of dH1
+    gemm<false, false, EPI_F32>(st, m->h1, m->d_in, batch, dH1, m->h1, d_x, m->d_in, g + L.W1, nullptr, m->d_in);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((m->h1 + 255) / 256)), dim3(256), 0, st, dH1, batch, m->h1,
+                       (const float *)nullptr, g + L.b1);
+    return check_launch("surr_backward");
+}
+
+extern "C" int surr_adam(const surr_model *m, float lr, float beta1, float beta2, float eps, int32_t step,
+                         void *stream) {
+    int rc = check_model(m, true);
+    if (rc) return rc;
+    LIGATE_REQUIRE(step >= 1 && lr > 0.0f && beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f &&
+                       eps > 0.0f,
+                   DOCK_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+    const Layout L = Layout::of(m->d_in, m->h1, m->h2);
+    const double c1 = 1.0 / (1.0 - pow((double)beta1, (double)step));
+    const double c2 = 1.0 / (1.0 - pow((double)beta2, (double)step));
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((L.n_master + 255) / 256)), dim3(256), 0, st, m->d_master, m->d_grad,
+                       m->d_adam_m, m->d_adam_v, L.n_master, lr, beta1, beta2, eps, (float)c1, (float)c2);
+    rc = check_launch("surr_adam");
+    if (rc) return rc;
+    return surr_cast(m, stream);
+}
+
+namespace ligate {
+__global__ void k_gather_rows(const uint16_t *__restrict__ src, const int32_t *__restrict__ idx, int64_t n_idx,
+                              int row, uint16_t *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_idx * row) return;
+    const int64_t r = i / row;
+    dst[i] = src[(int64_t)idx[r] * row + (i - r * row)];
+}
+__global__ void k_gather_f32(const float *__restrict__ src, const int32_t *__restrict__ idx, int64_t n_idx,
+                             float *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_idx) dst[i] = src[idx[i]];
+}
+}  // namespace ligate
+
+extern "C" int surr_gather(const uint16_t *d_x, const float *d_t, const int32_t *d_idx, int64_t n_idx, int32_t row,
+                           uint16_t *d_x_out, float *d_t_out, void *stream) {
+    LIGATE_REQUIRE(n_idx >= 0 && row >= 1 && d_idx, DOCK_ERR_INVALID_ARG, "bad gather arguments");
+    LIGATE_REQUIRE((d_x == nullptr) == (d_x_out == nullptr) && (d_t == nullptr) == (d_t_out == nullptr),
+                   DOCK_ERR_INVALID_ARG, "inputs and outputs go together");
+    if (n_idx == 0) return DOCK_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (d_x) {
+        const int64_t n = n_idx * row;
+        hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d_x, d_idx, n_idx, row,
+                           d_x_out);
+    }
+    if (d_t)
+        hipLaunchKernelGGL(k_gather_f32, dim3((unsigned)((n_idx + 255) / 256)), dim3(256), 0, st, d_t, d_idx, n_idx,
+                           d_t_out);
+    return check_launch("surr_gather");
+}

@@ -69,7 +69,7 @@ def load() -> ctypes.CDLL:
         lib.dock_grid_bytes.argtypes = [P(GridDesc), P(sz)]
         lib.dock_build_grids.argtypes = [P(GridDesc), vp, vp, i32, P(TypeParam), P(Potential), vp, vp]
         lib.dock_pack_ligands.argtypes = [vp, vp, vp, vp, vp, vp, i32, i64, i32, vp, P(sz), vp, vp]
-        lib.dock_screen.argtypes = [P(GridDesc), vp, vp, i32, i64, P(SearchDesc), vp, vp, vp, vp, vp, vp, P(sz), vp]
+        lib.dock_screen.argtypes = [P(GridDesc), vp, vp, i32, i64, P(SearchDesc), vp, vp, vp, vp, vp, vp, vp, P(sz), vp]
         lib.dock_topk.argtypes = [vp, vp, i64, i32, vp, vp, vp, P(sz), vp]
         lib.dock_score_poses.argtypes = [P(GridDesc), vp, vp, i32, i64, P(SearchDesc), vp, vp, vp, i64, vp, vp]
         lib.dock_error_string.restype = ctypes.c_char_p
@@ -156,16 +156,17 @@ def pack_ligands(atom_off, xyz, types, bond_off, bonds, rot, n_types: int, pack:
 def screen_ws_bytes(desc: GridDesc, n_lig: int, n_atoms: int, search: SearchDesc) -> int:
     out = ctypes.c_size_t()
     _check(load().dock_screen(ctypes.byref(desc), None, None, n_lig, n_atoms, ctypes.byref(search), None, None, None,
-                              None, None, None, ctypes.byref(out), None), "dock_screen(size)")
+                              None, None, None, None, ctypes.byref(out), None), "dock_screen(size)")
     return out.value
 
 
 def screen(desc: GridDesc, grids, pack, n_lig: int, n_atoms: int, search: SearchDesc, best_score, best_start,
-           best_steps, ws, start_scores=None, pose_count=None, stream=None):
+           best_steps, ws, start_scores=None, pose_count=None, stream=None, start_steps=None):
     size = ctypes.c_size_t(ws.numel() * ws.element_size())
     _check(load().dock_screen(ctypes.byref(desc), _ptr(grids), _ptr(pack), n_lig, n_atoms, ctypes.byref(search),
                               _ptr(best_score), _ptr(best_start), _ptr(best_steps), _ptr(start_scores),
-                              _ptr(pose_count), _ptr(ws), ctypes.byref(size), _stream(stream)), "dock_screen")
+                              _ptr(start_steps), _ptr(pose_count), _ptr(ws), ctypes.byref(size), _stream(stream)),
+           "dock_screen")
 
 
 def topk_ws_bytes(n: int, k: int) -> int:

@@ -316,6 +316,17 @@ def workload(name: str) -> Workload:
     raise ValueError(f"unknown workload {name!r}")
 
 
+def mlp_init(d_in: int = 512, h1: int = 1024, h2: int = 1024, seed: int = BASE_SEED) -> np.ndarray:
+    """Seeded initial master weights of the pre-filter network, flat FP32 in the order
+    W1 [h1, d_in], b1, W2 [h2, h1], b2, w3 [h2], b3: weights uniform in +-sqrt(6 / fan_in)
+    (Kaiming-uniform for ReLU layers; +-sqrt(3 / fan_in) for the linear output), biases zero."""
+    rng = np.random.default_rng([seed, 0x6D6C70])
+    W1 = rng.uniform(-1, 1, (h1, d_in)) * np.sqrt(6.0 / d_in)
+    W2 = rng.uniform(-1, 1, (h2, h1)) * np.sqrt(6.0 / h1)
+    w3 = rng.uniform(-1, 1, h2) * np.sqrt(3.0 / h2)
+    return np.concatenate([W1.ravel(), np.zeros(h1), W2.ravel(), np.zeros(h2), w3, np.zeros(1)]).astype(np.float32)
+
+
 def search_for(pocket: Pocket, base: Search, radius: float = 4.0) -> Search:
     """The same search centred on another pocket (translations follow the pocket centre)."""
     return Search(base.quat, translations(len(base.trans), radius, pocket.center), base.n_steps,

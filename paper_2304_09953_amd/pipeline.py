@@ -88,6 +88,7 @@ class ScreenResult:
     best_steps: torch.Tensor   # uint16 [n_lig, 16] (as int32 view on the host)
     pose_count: torch.Tensor   # uint64 [1] (int64 storage)
     start_scores: torch.Tensor | None
+    start_steps: torch.Tensor | None = None
 
 
 class Screener:
@@ -105,13 +106,15 @@ class Screener:
         self.pose_count = torch.empty(1, dtype=torch.int64, device=dev)
         self.start_scores = (torch.empty(n * search.n_starts, dtype=torch.float32, device=dev)
                              if start_scores else None)
+        self.start_steps = (torch.empty(n * search.n_starts * dock.MAX_TORSIONS, dtype=torch.int16, device=dev)
+                            if start_scores else None)
 
     def run(self, stream=None) -> ScreenResult:
         dock.screen(self.pocket.desc, self.pocket.grids, self.lib.pack, self.lib.n_lig, self.lib.n_atoms,
                     self.search.desc, self.best_score, self.best_start, self.best_steps, self.ws,
-                    self.start_scores, self.pose_count, stream)
+                    self.start_scores, self.pose_count, stream, self.start_steps)
         return ScreenResult(self.best_score, self.best_start, self.best_steps.view(self.lib.n_lig, -1),
-                            self.pose_count, self.start_scores)
+                            self.pose_count, self.start_scores, self.start_steps)
 
 
 def screen(pocket: DevicePocket, lib: DeviceLibrary, search: DeviceSearch, start_scores: bool = False):

@@ -9,7 +9,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ligate_dock.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("ligate_dock.h", "ligate_surrogate.h")]
 
 
 def _lib():
@@ -20,9 +20,14 @@ def _lib():
     return dock, dock.load()
 
 
-def declared_functions():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(dock_\w+)\s*\(", text, re.M)))
+def declared_functions(prefix="dock_"):
+    text = "".join(open(h).read() for h in HEADERS)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(" + prefix + r"\w+)\s*\(", text, re.M)))
+
+
+def test_every_header_is_covered():
+    import glob
+    assert sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))) == sorted(HEADERS)
 
 
 def test_header_declares_the_abi():
@@ -34,9 +39,28 @@ def test_header_declares_the_abi():
 
 def test_library_exports_every_declared_symbol():
     dock, lib = _lib()
-    for name in declared_functions():
+    from paper_2304_09953_amd import surrogate
+    for name in declared_functions("dock_") + declared_functions("surr_"):
         assert hasattr(lib, name), name
-    assert set(dock.EXPORTS) == set(declared_functions())
+    assert set(dock.EXPORTS) == set(declared_functions("dock_"))
+    assert set(surrogate.SURR_EXPORTS) == set(declared_functions("surr_"))
+
+
+def test_surrogate_argument_errors():
+    _, lib = _lib()
+    from paper_2304_09953_amd import surrogate as SG
+    lib = SG._lib()
+    nm, nb = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.surr_param_count(512, 1024, 1024, ctypes.byref(nm), ctypes.byref(nb)) == 0
+    assert nm.value == 1024 * 512 + 1024 + 1024 * 1024 + 1024 + 1024 + 1
+    assert nb.value == 1024 * 512 + 1024 * 1024 + 1024
+    bad = SG.SurrModel(500, 1024, 1024, 1, 1, 1, 1, 1)
+    sz = ctypes.c_size_t()
+    assert lib.surr_forward(ctypes.byref(bad), None, 8, None, None, ctypes.byref(sz), None) == -1
+    good = SG.SurrModel(512, 1024, 1024, 1, 1, 1, 1, 1)
+    assert lib.surr_forward(ctypes.byref(good), None, 8, None, None, ctypes.byref(sz), None) == 0
+    assert lib.surr_backward(ctypes.byref(good), None, None, 30, None, None, ctypes.byref(sz), None) == -1
+    assert lib.surr_features(None, None, None, None, 5, 10, 17, None, None, None, None, None) == -2
 
 
 def test_error_strings():
@@ -77,11 +101,11 @@ def test_size_queries_and_argument_errors():
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: size queries return before any device work
     s = dock.SearchDesc(4, fake, 2, fake, 64, 2.5, 10.0, 0, 0)
     assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(s), None, None, None, None,
-                           None, None, ctypes.byref(sz), None) == 0
+                           None, None, None, ctypes.byref(sz), None) == 0
     assert sz.value > 0
     s_bad = dock.SearchDesc(4, fake, 2, fake, 2048, 2.5, 10.0, 0, 0)
     assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(s_bad), None, None, None, None,
-                           None, None, ctypes.byref(sz), None) == -2
+                           None, None, None, ctypes.byref(sz), None) == -2
     assert lib.dock_topk(None, None, 100, 10, None, None, None, ctypes.byref(sz), None) == 0
     assert lib.dock_topk(None, None, 100, 101, None, None, None, ctypes.byref(sz), None) == -1
     assert lib.dock_topk(None, None, 0, 1, None, None, None, ctypes.byref(sz), None) == -1

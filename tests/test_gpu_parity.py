@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from parity import TAU, check_exact_and_valid, check_optimal, check_per_start, tol, tol_pose
+from parity import TAU, check_exact_and_valid, check_optimal, check_per_start, tol, tol_fp32, tol_pose
 from paper_2304_09953_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -160,7 +160,8 @@ def test_score_poses_vs_oracle(P, p48):
     ref = oracle.score_poses(pocket, G, ligs, W.search, lig, start, steps)
     err = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
     say(f"score_poses max rel err {err.max():.3g}, median {np.median(err):.3g}")
-    assert np.all(np.abs(got - ref) <= tol_pose(ref, ligs.n_atoms[lig]))
+    assert np.all(np.abs(got - ref) <= tol_fp32(ref, ligs.n_atoms[lig], G, pocket.dims))
+    assert np.mean(np.abs(got - ref) <= tol_pose(ref, ligs.n_atoms[lig])) >= 0.999
 
 
 # ------------------------------------------------------------------------------------------------
@@ -177,6 +178,7 @@ def _screen(P, dp, ligs, search, start_scores=False, **kw):
            "status": lib.status.cpu().numpy()}
     if start_scores:
         out["finals"] = r.start_scores.cpu().numpy().reshape(ligs.n_lig, -1).astype(np.float64)
+        out["start_steps"] = P.steps_numpy(r.start_steps).reshape(ligs.n_lig, search.n_starts, -1)
     return out
 
 
@@ -185,9 +187,20 @@ def test_screen_pocket48_lib100_full(P, p48):
     say("screen pocket48-lib100 (100 ligands, 512 starts, S=64) with per-start scores")
     g = _screen(P, dp, ligs, W.search, start_scores=True)
     orc = oracle.dock(pocket, G, ligs, W.search, per_start=True)
-    st = check_per_start(g["finals"], orc, ligs.n_atoms)
+    try:
+        st = check_per_start(pocket, G, ligs, W.search, g["finals"], g["start_steps"], orc)
+    except AssertionError:
+        bad = np.argwhere(np.abs(g["finals"] - orc["finals"]) > 1e-3 * np.maximum(1, np.abs(orc["finals"])))[:4]
+        for l, p in bad:
+            direct = P.score_poses(dp, P.DeviceLibrary(ligs), P.DeviceSearch(W.search), [l], [p],
+                                   g["start_steps"][l, p][None]).cpu().numpy()[0]
+            say(f"diverging start ({l}, {p}): GPU incremental {g['finals'][l, p]!r}, GPU from-scratch {direct!r}, "
+                f"oracle {orc['finals'][l, p]!r}, GPU steps {g['start_steps'][l, p, :4]}, "
+                f"oracle steps {orc['start_steps'][l, p, :4]}")
+        raise
     say(f"per-start: {st}")
-    assert st["compared"] >= 0.5 * ligs.n_lig * W.search.n_starts
+    assert st["agree"] >= 0.99 * st["starts"]
+    assert st["agree_typical"] >= 0.999 * st["agree"]
     # internal consistency: the best is the lowest per-start final, ties to the lowest start
     assert np.array_equal(g["score"], g["finals"].min(1))
     assert np.array_equal(g["start"], np.argmin(g["finals"], 1))
@@ -245,7 +258,7 @@ def test_screen_is_deterministic_and_tuning_invariant(P, p48):
         say(f"screen pocket48-lib100 subset, tuning {kw}")
         runs.append(_screen(P, dp, sub, W.search, start_scores=True, **kw))
     for r in runs[1:]:
-        for key in ("score", "start", "steps", "finals"):
+        for key in ("score", "start", "steps", "finals", "start_steps"):
             assert np.array_equal(r[key], runs[0][key]), key
 
 

@@ -1,0 +1,127 @@
+"""Parity of the pre-filter kernels (through the C ABI) with the FP64 NumPy oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import surrogate as S
+from paper_2304_09953_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_09953_amd import pipeline as P
+    from paper_2304_09953_amd import surrogate as SG
+    return P, SG
+
+
+def _bits_to_f64(t: torch.Tensor) -> np.ndarray:
+    u = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-30))
+
+
+def test_features_match_oracle(env):
+    P, SG = env
+    ligs = I.make_ligands(300, I.DIST_HEAVY_TAIL, 16, stream="test")
+    say("features of 300 ligands (n up to 120)")
+    lib = P.DeviceLibrary(ligs)
+    F, Fb = SG.features(lib)
+    ref = S.features(ligs)
+    got = F.cpu().numpy().astype(np.float64)
+    # counts are integers decided identically on both sides; log1p in FP32 vs FP64
+    assert np.allclose(got, ref, rtol=2e-7, atol=1e-7)
+    assert np.array_equal(np.round(np.expm1(got)), np.round(np.expm1(ref)))
+    assert np.array_equal(_bits_to_f64(Fb), S.bf16_round(got))
+    mean, istd = SG.feature_stats(F)
+    m_ref, i_ref = S.feature_stats(ref)
+    assert np.allclose(mean.cpu().numpy(), m_ref, rtol=1e-5, atol=1e-6)
+    assert np.allclose(istd.cpu().numpy(), i_ref, rtol=1e-4, atol=1e-6)
+    Fn, _ = SG.features(lib, mean, istd)
+    assert np.allclose(Fn.cpu().numpy(), S.normalise(ref, mean.cpu().numpy().astype(np.float64),
+                                                     istd.cpu().numpy().astype(np.float64)), rtol=1e-4, atol=1e-4)
+
+
+def test_invalid_ligands_get_zero_features(env):
+    P, SG = env
+    from test_gpu_parity import _edge_library
+    ligs = _edge_library()
+    lib = P.DeviceLibrary(ligs)
+    st = lib.status.cpu().numpy()
+    F, _ = SG.features(lib)
+    F = F.cpu().numpy()
+    assert np.all(F[st != 0] == 0)
+    ok = np.flatnonzero((st == 0) & (np.array([t.max() for t in (ligs.ligand(i)[1] for i in range(ligs.n_lig))]) < 16))
+    assert np.allclose(F[ok], S.features(ligs.subset(ok)), rtol=2e-7, atol=1e-7)
+
+
+@pytest.mark.parametrize("dims,batch", [((64, 64, 64), 40), ((512, 1024, 1024), 1024), ((128, 192, 64), 97)])
+def test_forward_matches_bf16_mirror(env, dims, batch):
+    P, SG = env
+    d, h1, h2 = dims
+    rng = np.random.default_rng(d + batch)
+    init = I.mlp_init(d, h1, h2, seed=d)
+    init[d * h1:d * h1 + h1] = rng.normal(size=h1) * 0.1  # non-zero biases
+    m = SG.Model(init, d, h1, h2)
+    X = rng.normal(size=(batch, d)).astype(np.float32)
+    xb = torch.as_tensor(S.bf16_bits(X).view(np.int16)).cuda()
+    say(f"forward {dims} batch {batch}")
+    y = m.forward(xb).cpu().numpy()
+    y_ref, _ = S.forward(S.Params(d, h1, h2), init.astype(np.float64), X)
+    say(f"forward rel err {_rel(y, y_ref):.3g}")
+    assert _rel(y, y_ref) < 2e-3
+
+
+def test_backward_and_adam_match_oracle(env):
+    P, SG = env
+    d, h1, h2, B = 512, 1024, 1024, 256
+    rng = np.random.default_rng(5)
+    init = I.mlp_init(d, h1, h2, seed=7)
+    init[d * h1:d * h1 + h1] = rng.normal(size=h1) * 0.05
+    m = SG.Model(init, d, h1, h2)
+    X = rng.normal(size=(B, d)).astype(np.float32)
+    t = rng.normal(size=B).astype(np.float32)
+    xb = torch.as_tensor(S.bf16_bits(X).view(np.int16)).cuda()
+    tt = torch.as_tensor(t).cuda()
+    loss = torch.empty(1, device="cuda")
+    say("backward 512-1024-1024 batch 256")
+    m.backward(xb, tt, loss)
+    g = m.grad.cpu().numpy().astype(np.float64)
+    Pm = S.Params(d, h1, h2)
+    l_ref, g_ref = S.backward(Pm, init.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
+    assert abs(loss.item() - l_ref) <= 1e-3 * max(1.0, l_ref)
+    for name, gp, gr in zip(Pm.shapes, Pm.split(g).values(), Pm.split(g_ref).values()):
+        say(f"grad {name[0]} rel err {_rel(gp, gr):.3g}")
+        assert _rel(gp, gr) < 5e-3, name
+    say("Adam step")
+    m.adam(1e-3)
+    w1 = m.master.cpu().numpy().astype(np.float64)
+    w_ref, _, _ = S.adam(init.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1)
+    assert np.allclose(w1, w_ref, rtol=1e-6, atol=1e-9)
+    assert np.array_equal(_bits_to_f64(m.bf16[:d * h1]), S.bf16_round(w1[:d * h1]))
+
+
+def test_training_overfits_a_small_set(env):
+    P, SG = env
+    rng = np.random.default_rng(3)
+    n, d = 512, 512
+    X = rng.normal(size=(n, d)).astype(np.float32)
+    t = (np.tanh(X[:, :8].sum(1) / 3) + 0.1 * rng.normal(size=n)).astype(np.float32)
+    m = SG.Model(I.mlp_init(d, 1024, 1024, seed=1))
+    xb = torch.as_tensor(S.bf16_bits(X).view(np.int16)).cuda()
+    say("train 512 samples x 40 epochs")
+    hist = SG.train(m, xb, torch.as_tensor(t).cuda(), epochs=40, batch=128, lr=1e-3, seed=0)
+    say(f"loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    assert hist[-1] < 0.1 * hist[0]
+    y = m.predict(xb).cpu().numpy()
+    assert S.r2(y, t) > 0.9
