@@ -1,0 +1,248 @@
+"""Batched screening of uneven ligand libraries (the batch redesign of the paper's §3.3).
+
+Ligands are clustered by size into buckets; each bucket is screened in chunks of fixed capacity
+whose launch parameters (rigid starts per work item, wavefronts per block) come from the
+autotuner, and each chunk's pack -> screen -> top-k merge sequence is captured once into a
+hipGraph and replayed with the next chunk's ligands copied into the same device buffers.  Every
+step runs in the library's kernels through the C ABI; this module only orders the calls, owns the
+buffers and times candidate launch parameters.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import dock
+from . import pipeline as P
+
+TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
+BUCKET_EDGES = (25, 41, 71)  # atom-count buckets: <= 24, 25-40, 41-70, >= 71
+CANDIDATES = [(p, w) for p in (32, 64, 128, 256) for w in (1, 2, 4, 8) if p >= w]
+
+
+def size_bucket(n_atoms: np.ndarray) -> np.ndarray:
+    return np.searchsorted(np.asarray(BUCKET_EDGES), np.asarray(n_atoms), side="right")
+
+
+def arch_name() -> str:
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:  # noqa: BLE001 - no device
+        return "unknown"
+
+
+def _key(arch: str, dims, S: int, bucket: int) -> str:
+    return f"{arch}|{dims[0]}x{dims[1]}x{dims[2]}|S{S}|b{bucket}"
+
+
+# ------------------------------------------------------------------------------------------------
+# Autotuner
+# ------------------------------------------------------------------------------------------------
+
+def time_screen(pocket_dev, lib_dev, search, starts_per_item: int, waves_per_block: int, reps: int = 2) -> float:
+    """Seconds per dock_screen launch with the given launch parameters (median of reps)."""
+    ds = P.DeviceSearch(search, starts_per_item=starts_per_item, waves_per_block=waves_per_block)
+    scr = P.Screener(pocket_dev, lib_dev, ds)
+    scr.run()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        scr.run()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    return float(np.median(ts))
+
+
+def autotune(pocket_dev, ligs, search, per_bucket: int = 256, log=None) -> dict:
+    """Times every candidate (starts per item, waves per block) on a sample of each size bucket
+    and keeps the fastest.  Returns {bucket: {"starts_per_item", "waves_per_block", "s_per_ligand",
+    "candidates": {...}}}."""
+    b = size_bucket(ligs.n_atoms)
+    out = {}
+    rng = np.random.default_rng(0)
+    for bucket in range(len(BUCKET_EDGES) + 1):
+        idx = np.flatnonzero(b == bucket)
+        if len(idx) == 0:
+            continue
+        sample = np.sort(rng.choice(idx, min(per_bucket, len(idx)), replace=False))
+        lib_dev = P.DeviceLibrary(ligs.subset(sample))
+        res = {}
+        for p, w in CANDIDATES:
+            res[f"{p}x{w}"] = time_screen(pocket_dev, lib_dev, search, p, w) / len(sample)
+            if log:
+                log(f"bucket {bucket}: starts/item {p}, waves/block {w}: {res[f'{p}x{w}'] * 1e6:.1f} us/ligand")
+        best = min(res, key=res.get)
+        p, w = (int(v) for v in best.split("x"))
+        out[bucket] = {"starts_per_item": p, "waves_per_block": w, "s_per_ligand": res[best], "candidates": res,
+                       "sample": int(len(sample))}
+    return out
+
+
+def save_table(table: dict, arch: str, dims, S: int, path: str | None = None) -> str:
+    path = path or os.path.join(TUNING_DIR, f"{arch}.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    for bucket, v in table.items():
+        data[_key(arch, dims, S, int(bucket))] = {k: v[k] for k in ("starts_per_item", "waves_per_block",
+                                                                    "s_per_ligand", "sample")}
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    json.dump(data, open(path, "w"), indent=1, sort_keys=True)
+    return path
+
+
+def lookup(arch: str, dims, S: int, bucket: int, path: str | None = None) -> tuple[int, int]:
+    """Tuned (starts_per_item, waves_per_block) or the library's defaults (0, 0)."""
+    path = path or os.path.join(TUNING_DIR, f"{arch}.json")
+    try:
+        v = json.load(open(path))[_key(arch, dims, S, bucket)]
+        return int(v["starts_per_item"]), int(v["waves_per_block"])
+    except (OSError, KeyError, ValueError):
+        return 0, 0
+
+
+# ------------------------------------------------------------------------------------------------
+# hipGraph-captured chunks
+# ------------------------------------------------------------------------------------------------
+
+@dataclass
+class ChunkShape:
+    n_lig: int      # ligand capacity of a chunk
+    n_atoms: int    # atom capacity of a chunk
+
+
+class ChunkPipeline:
+    """Fixed device buffers for one (pocket, launch parameters, chunk shape) and a hipGraph of
+    pack -> screen -> merge of the chunk's best scores into a running top-k."""
+
+    def __init__(self, pocket_dev, search, shape: ChunkShape, n_types: int, k: int, starts_per_item: int = 0,
+                 waves_per_block: int = 0, use_graph: bool = True):
+        dev = pocket_dev.grids.device
+        self.pocket, self.shape, self.k, self.n_types = pocket_dev, shape, k, n_types
+        L, A = shape.n_lig, shape.n_atoms
+        self.atom_off = torch.zeros(L + 1, dtype=torch.int32, device=dev)
+        self.bond_off = torch.zeros(L + 1, dtype=torch.int32, device=dev)
+        self.xyz = torch.zeros(3 * A, dtype=torch.float32, device=dev)
+        self.types = torch.zeros(A, dtype=torch.uint8, device=dev)
+        self.bonds = torch.zeros(2 * max(A, 1), dtype=torch.int32, device=dev)
+        self.rot = torch.zeros(max(A, 1), dtype=torch.uint8, device=dev)
+        self.pack = torch.empty(dock.pack_bytes(L, A, n_types), dtype=torch.uint8, device=dev)
+        self.status = torch.empty(L, dtype=torch.int32, device=dev)
+        self.search = P.DeviceSearch(search, starts_per_item=starts_per_item, waves_per_block=waves_per_block)
+        self.ws = torch.empty(dock.screen_ws_bytes(pocket_dev.desc, L, A, self.search.desc), dtype=torch.uint8,
+                              device=dev)
+        # merge buffer: [running top-k | this chunk's best scores], with global ligand ids
+        self.scores = torch.full((k + L,), float("inf"), dtype=torch.float32, device=dev)
+        self.ids = torch.full((k + L,), 2 ** 31 - 1, dtype=torch.int32, device=dev)
+        self.best_start = torch.empty(L, dtype=torch.int32, device=dev)
+        self.best_steps = torch.empty(L * dock.MAX_TORSIONS, dtype=torch.int16, device=dev)
+        self.top_s = torch.empty(k, dtype=torch.float32, device=dev)
+        self.top_i = torch.empty(k, dtype=torch.int32, device=dev)
+        self.topk_ws = torch.empty(dock.topk_ws_bytes(k + L, k), dtype=torch.uint8, device=dev)
+        self.graph = None
+        if use_graph:
+            self._capture()
+
+    def _enqueue(self):
+        L, A = self.shape.n_lig, self.shape.n_atoms
+        dock.pack_ligands(self.atom_off, self.xyz, self.types, self.bond_off, self.bonds, self.rot, self.n_types,
+                          self.pack, self.status)
+        dock.screen(self.pocket.desc, self.pocket.grids, self.pack, L, A, self.search.desc, self.scores[self.k:],
+                    self.best_start, self.best_steps, self.ws)
+        dock.topk(self.scores, self.k, self.top_s, self.top_i, self.topk_ws, self.ids)
+        self.scores[:self.k].copy_(self.top_s)
+        self.ids[:self.k].copy_(self.top_i)
+
+    def _capture(self):
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):  # warm-up outside the graph (first-launch host work)
+            self._enqueue()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.reset()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._enqueue()
+        torch.cuda.synchronize()
+
+    def reset(self):
+        self.scores.fill_(float("inf"))
+        self.ids.fill_(2 ** 31 - 1)
+
+    def load(self, ligs, ids: np.ndarray):
+        """Copies a chunk (at most the capacity) into the fixed buffers; unused ligand slots become
+        empty ligands (status n_atoms, score +inf)."""
+        L, A = self.shape.n_lig, self.shape.n_atoms
+        n, a = ligs.n_lig, int(ligs.atom_off[-1])
+        assert n <= L and a <= A, (n, a, L, A)
+        off = np.full(L + 1, a, dtype=np.int32)
+        off[:n + 1] = ligs.atom_off
+        boff = np.full(L + 1, int(ligs.bond_off[-1]), dtype=np.int32)
+        boff[:n + 1] = ligs.bond_off
+        self.atom_off.copy_(torch.from_numpy(off))
+        self.bond_off.copy_(torch.from_numpy(boff))
+        self.xyz[:3 * a].copy_(torch.from_numpy(ligs.xyz.reshape(-1)))
+        self.types[:a].copy_(torch.from_numpy(ligs.types))
+        e = int(ligs.bond_off[-1])
+        if e:
+            self.bonds[:2 * e].copy_(torch.from_numpy(ligs.bonds.reshape(-1)))
+            self.rot[:e].copy_(torch.from_numpy(ligs.rot))
+        gid = np.full(L, 2 ** 31 - 1, dtype=np.int32)
+        gid[:n] = ids
+        self.ids[self.k:].copy_(torch.from_numpy(gid))
+
+    def run(self):
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self._enqueue()
+
+
+def chunk_shape_for(ligs, idx: np.ndarray, chunk: int) -> ChunkShape:
+    """Capacity that fits every chunk of `chunk` ligands taken in order from idx."""
+    n = ligs.n_atoms[idx]
+    if len(n) == 0:
+        return ChunkShape(1, 1)
+    sums = [int(n[s:s + chunk].sum()) for s in range(0, len(n), chunk)]
+    return ChunkShape(min(chunk, len(n)), max(sums))
+
+
+def screen_buckets(pocket_dev, search, ligs, k: int = 1000, chunk: int = 16384, tuned: bool = True,
+                   use_graph: bool = True, log=None):
+    """Screens a library against one pocket bucket by bucket in graph-replayed chunks, merging
+    into one running top-k.  Returns (top scores, top global ids, per-ligand best scores)."""
+    arch = arch_name()
+    buckets = size_bucket(ligs.n_atoms)
+    best = np.full(ligs.n_lig, np.inf, dtype=np.float32)
+    top_s = np.full(k, np.inf, dtype=np.float32)
+    top_i = np.full(k, 2 ** 31 - 1, dtype=np.int32)
+    for bucket in range(len(BUCKET_EDGES) + 1):
+        idx = np.flatnonzero(buckets == bucket)
+        if len(idx) == 0:
+            continue
+        p, w = lookup(arch, pocket_dev.pocket.dims, search.n_steps, bucket) if tuned else (0, 0)
+        pipe = ChunkPipeline(pocket_dev, search, chunk_shape_for(ligs, idx, chunk), ligs.n_types, k, p, w, use_graph)
+        pipe.reset()
+        pipe.scores[:k].copy_(torch.from_numpy(top_s))
+        pipe.ids[:k].copy_(torch.from_numpy(top_i))
+        t0 = time.perf_counter()
+        for s in range(0, len(idx), chunk):
+            sel = idx[s:s + chunk]
+            pipe.load(ligs.subset(sel), ligs.ids[sel].astype(np.int32))
+            pipe.run()
+            best[sel] = pipe.scores[k:k + len(sel)].cpu().numpy()
+        torch.cuda.synchronize()
+        top_s = pipe.scores[:k].cpu().numpy()
+        top_i = pipe.ids[:k].cpu().numpy()
+        if log:
+            log(f"bucket {bucket}: {len(idx)} ligands, starts/item {p}, waves/block {w}, "
+                f"{time.perf_counter() - t0:.2f} s")
+    return top_s, top_i, best

@@ -47,7 +47,8 @@ struct SearchC {
     const float *__restrict__ quat;
     const float *__restrict__ trans;
     int n_quat, n_trans, S, QT;
-    float cut, cut2_keep, w;   // clash in grid units: cut-off / h, (cut-off / h + margin)^2, weight h^2
+    float cut, cut2, cut2_keep, w;  // clash in grid units: cut-off / h, its square, (cut-off / h + margin)^2,
+                                    // weight h^2
 };
 
 // Coordinates inside a start are in grid units (x - origin) / spacing throughout: the map is a
@@ -379,14 +380,18 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
         for (int j = 0; j < APL; ++j) e[j] = 0.0f;
         int nsurv = 0;
 
+        // A kept pair clashes only on part of its circle: the penalty of an angle group is
+        // evaluated only when some lane of the wavefront is inside the cut-off there.
         auto flush = [&](int cnt) {
             for (int q = 0; q < cnt; ++q) {
                 const float4 acd = W.surv[q];
 #pragma unroll
                 for (int j = 0; j < APL; ++j) {
                     const float d2 = fmaxf(fmaf(acd.y, cs[j], fmaf(acd.z, sn[j], acd.x)), 0.0f);
-                    const float t = fmaxf(s.cut - __builtin_amdgcn_sqrtf(d2), 0.0f);
-                    e[j] = fmaf(s.w * t, t, e[j]);
+                    if (__ballot(d2 < s.cut2)) {
+                        const float t = fmaxf(s.cut - __builtin_amdgcn_sqrtf(d2), 0.0f);
+                        e[j] = fmaf(s.w * t, t, e[j]);
+                    }
                 }
             }
         };
@@ -777,6 +782,8 @@ static SearchC make_search(const dock_search *d, float spacing) {
     s.S = d->n_steps;
     s.QT = d->n_quat * d->n_trans;
     s.cut = d->clash_cut / spacing;
+    // a lane whose d2 is below (cut + margin)^2 is evaluated; beyond it the penalty is zero
+    s.cut2 = (s.cut + 1e-3f) * (s.cut + 1e-3f);
     const float keep = s.cut + 1e-3f;  // pairs this close somewhere on the circle are kept
     s.cut2_keep = keep * keep;
     s.w = d->clash_w * spacing * spacing;

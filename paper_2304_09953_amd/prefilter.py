@@ -1,0 +1,158 @@
+"""Learned pre-filter workflow: label, train, predict, select, dock (the paper's §3.5 engines fed
+by data the workflow itself generates, §2).
+
+1. Labels: best docking scores of a training library from the GPU screen.
+2. Features -> statistics -> normalised BF16 inputs; training with Adam on the matrix cores.
+3. Held-out R^2 and Spearman correlation.
+4. Filtered screening of a library streamed in chunks: features and predictions for every ligand,
+   global top fraction by prediction, docking of the selected ligands only.
+5. Recall of the true top 1 % of a fully docked sample.
+
+Every computational step runs in the library's kernels; this module orders the calls and moves
+ligand chunks between host and device.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import inputs as I
+from . import pipeline as P
+from . import surrogate as SG
+
+
+def dock_scores(pocket_dev, search_dev, ligs, chunk: int = 100_000, log=None) -> np.ndarray:
+    """Best docking score of every ligand (+inf for invalid ones)."""
+    out = np.empty(ligs.n_lig, dtype=np.float32)
+    for s in range(0, ligs.n_lig, chunk):
+        sub = ligs.subset(np.arange(s, min(s + chunk, ligs.n_lig))) if ligs.n_lig > chunk else ligs
+        r = P.screen(pocket_dev, P.DeviceLibrary(sub), search_dev)
+        out[s:s + sub.n_lig] = r.best_score.cpu().numpy()
+        if log:
+            log(f"docked {s + sub.n_lig}/{ligs.n_lig}")
+    return out
+
+
+def library_chunk(dist, n_types, first_id: int, n: int, stream: str = "lib"):
+    return I.make_ligands(n, dist, n_types, stream=stream, first_id=first_id)
+
+
+@dataclass
+class Surrogate:
+    model: SG.Model
+    mean: torch.Tensor
+    istd: torch.Tensor
+    y_mean: float
+    y_std: float
+    metrics: dict = field(default_factory=dict)
+
+    def predict_library(self, lib_dev) -> np.ndarray:
+        """Predicted best score of every ligand of a DeviceLibrary, as the network's z-score (a
+        monotone map of the score, so rankings are those of the scores); +inf where the ligand's
+        status is not OK."""
+        _, xb = SG.features(lib_dev, self.mean, self.istd, f32=False, bf16=True)
+        z = self.model.predict(xb).cpu().numpy()
+        return np.where(lib_dev.status.cpu().numpy() == 0, z, np.float32(np.inf))
+
+
+def train_surrogate(pocket_dev, search_dev, train_ligs, labels: np.ndarray | None = None, n_holdout: int = 40_000,
+                    epochs: int = 30, batch: int = 1024, lr: float = 1e-3, seed: int = 0, log=None) -> Surrogate:
+    """Labels the training library by docking (unless given), trains on all but the last
+    n_holdout ligands (feature statistics from the training part only) and reports held-out R^2
+    and Spearman.  The generated libraries hold valid ligands only."""
+    t0 = time.perf_counter()
+    if labels is None:
+        labels = dock_scores(pocket_dev, search_dev, train_ligs, log=log)
+    t_label = time.perf_counter() - t0
+    lib = P.DeviceLibrary(train_ligs)
+    assert np.all(lib.status.cpu().numpy() == 0) and np.all(np.isfinite(labels))
+    n_tr = train_ligs.n_lig - n_holdout
+    F, _ = SG.features(lib, bf16=False)
+    mean, istd = SG.feature_stats(F[:n_tr])
+    _, Xb = SG.features(lib, mean, istd, f32=False, bf16=True)
+    y = labels.astype(np.float64)
+    y_mean, y_std = float(y[:n_tr].mean()), float(y[:n_tr].std())
+    z = torch.as_tensor(((y - y_mean) / y_std).astype(np.float32), device=F.device)
+    model = SG.Model(I.mlp_init(seed=seed))
+    Xtr, ztr = Xb[:n_tr], z[:n_tr]
+    t1 = time.perf_counter()
+    hist = SG.train(model, Xtr, ztr, epochs=epochs, batch=batch, lr=lr, seed=seed, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    s = Surrogate(model, mean, istd, y_mean, y_std)
+    metrics = {"n_train": int(n_tr), "n_holdout": int(n_holdout), "epochs": epochs, "batch": batch,
+               "label_seconds": t_label, "train_seconds": t_train, "loss_first_epoch": hist[0],
+               "loss_last_epoch": hist[-1]}
+    if n_holdout:
+        from scipy.stats import spearmanr
+        pred = model.predict(Xb[n_tr:]).cpu().numpy().astype(np.float64) * y_std + y_mean
+        yh = y[n_tr:]
+        metrics["holdout_r2"] = float(1 - np.sum((pred - yh) ** 2) / np.sum((yh - yh.mean()) ** 2))
+        metrics["holdout_spearman"] = float(spearmanr(pred, yh).statistic)
+    s.metrics = metrics
+    return s
+
+
+def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, n_lib: int, chunk: int, frac: float,
+                    stream: str = "lib", sample_every: int = 0, log=None) -> dict:
+    """Predicts every ligand of the streamed library and docks the global top `frac` by
+    prediction.  With sample_every > 0 the ligands whose id is a multiple of it are also docked in
+    full during the same pass (the recall sample; timed separately).  Returns ids, scores, timings."""
+    preds = np.empty(n_lib, dtype=np.float32)
+    t_gen = t_pred = t_sample = 0.0
+    s_ids, s_scores = [], []
+    for s in range(0, n_lib, chunk):
+        g0 = time.perf_counter()
+        ligs = library_chunk(dist, n_types, s, min(chunk, n_lib - s), stream)
+        t_gen += time.perf_counter() - g0
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        preds[s:s + ligs.n_lig] = sur.predict_library(P.DeviceLibrary(ligs))
+        t_pred += time.perf_counter() - p0
+        if sample_every:
+            loc = np.flatnonzero(ligs.ids % sample_every == 0)
+            sub = ligs.subset(loc)
+            torch.cuda.synchronize()
+            d0 = time.perf_counter()
+            s_scores.append(P.screen(pocket_dev, P.DeviceLibrary(sub), search_dev).best_score.cpu().numpy())
+            t_sample += time.perf_counter() - d0
+            s_ids.append(sub.ids)
+        if log:
+            log(f"predicted {s + ligs.n_lig}/{n_lib}" + (f", docked sample {sum(map(len, s_ids))}" if sample_every else ""))
+    n_sel = int(round(frac * n_lib))
+    p0 = time.perf_counter()
+    _, sel_ids = P.topk(torch.as_tensor(preds, device="cuda"), n_sel)
+    sel = np.sort(sel_ids.cpu().numpy().astype(np.int64))
+    t_pred += time.perf_counter() - p0
+    # dock the selection, regenerated chunk by chunk
+    scores = np.empty(len(sel), dtype=np.float32)
+    t_dock = 0.0
+    for s in range(0, n_lib, chunk):
+        part = (sel >= s) & (sel < s + chunk)
+        if not part.any():
+            continue
+        g0 = time.perf_counter()
+        ligs = library_chunk(dist, n_types, s, min(chunk, n_lib - s), stream).subset(sel[part] - s)
+        t_gen += time.perf_counter() - g0
+        torch.cuda.synchronize()
+        d0 = time.perf_counter()
+        scores[part] = P.screen(pocket_dev, P.DeviceLibrary(ligs), search_dev).best_score.cpu().numpy()
+        t_dock += time.perf_counter() - d0
+        if log:
+            log(f"docked selection up to id {s + chunk}")
+    out = {"selected_ids": sel, "selected_scores": scores, "predictions": preds, "seconds_predict": t_pred,
+           "seconds_dock_selected": t_dock, "seconds_generate_on_host": t_gen, "n_selected": len(sel)}
+    if sample_every:
+        out.update(sample_ids=np.concatenate(s_ids), sample_scores=np.concatenate(s_scores),
+                   seconds_dock_sample=t_sample)
+    return out
+
+
+def recall_top(sample_ids: np.ndarray, sample_scores: np.ndarray, selected_ids: np.ndarray, frac: float = 0.01):
+    k = max(1, int(round(frac * len(sample_ids))))
+    order = np.lexsort((sample_ids, sample_scores))[:k]
+    top = set(sample_ids[order].tolist())
+    return len(top & set(selected_ids.tolist())) / k

@@ -150,19 +150,17 @@ def train(model: Model, X_bf16: torch.Tensor, t: torch.Tensor, epochs: int = 30,
     dev = X_bf16.device
     xb = torch.empty((batch, X_bf16.shape[1]), dtype=torch.int16, device=dev)
     tb = torch.empty(batch, dtype=torch.float32, device=dev)
-    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    nb = n // batch
+    losses = torch.empty(max(nb, 1), dtype=torch.float32, device=dev)  # one slot per step of an epoch
     rng = np.random.default_rng(seed)
     hist = []
     for ep in range(epochs):
         perm = torch.as_tensor(rng.permutation(n).astype(np.int32)).to(dev)
-        acc = torch.zeros(1, dtype=torch.float64, device=dev)
-        nb = n // batch
         for b in range(nb):
             gather(X_bf16, t, perm[b * batch:(b + 1) * batch], xb, tb)
-            model.backward(xb, tb, loss)
+            model.backward(xb, tb, losses[b:b + 1])
             model.adam(lr)
-            acc += loss
-        hist.append(float(acc.item()) / max(nb, 1))
+        hist.append(float(losses[:nb].cpu().numpy().astype(np.float64).mean()) if nb else float("nan"))
         if log:
             log(f"epoch {ep + 1}/{epochs}: loss {hist[-1]:.4f}")
     return hist

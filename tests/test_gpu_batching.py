@@ -1,0 +1,114 @@
+"""Bucketed, autotuned, hipGraph-replayed chunked screening equals one eager screen."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from parity import check_exact_and_valid
+from paper_2304_09953_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_09953_amd import batching as Bt
+    from paper_2304_09953_amd import pipeline as P
+    return P, Bt
+
+
+@pytest.fixture(scope="module")
+def uneven():
+    W = I.workload("pockets4-lib250k")
+    lib = W.ligands(n_lig=20000)
+    n = lib.n_atoms
+    rng = np.random.default_rng(4)
+    pick = np.sort(np.concatenate([rng.choice(np.flatnonzero(n < 80), 700, replace=False),
+                                   rng.choice(np.flatnonzero(n >= 80), 100, replace=False)]))
+    return W, lib.subset(pick)
+
+
+def test_graph_chunks_equal_eager_screen_on_all_pockets(env, uneven):
+    P, Bt = env
+    W, ligs = uneven
+    k = 100
+    for pi, pocket in enumerate(W.pockets):
+        srch = I.search_for(pocket, W.search)
+        say(f"pocket {pi} {pocket.dims}: eager screen of {ligs.n_lig} ligands (5% at 80-120 atoms)")
+        dp = P.DevicePocket(pocket)
+        r = P.screen(dp, P.DeviceLibrary(ligs), P.DeviceSearch(srch))
+        torch.cuda.synchronize()
+        eager = r.best_score.cpu().numpy()
+        say(f"pocket {pi}: bucketed graph-replayed chunks")
+        top_s, top_i, best = Bt.screen_buckets(dp, srch, ligs, k=k, chunk=96, tuned=False, use_graph=True)
+        assert np.array_equal(best, eager)  # identical per-start arithmetic in any launch
+        ref_s, ref_i = oracle.topk(eager, k, ligs.ids)
+        assert np.array_equal(top_i, ref_i.astype(np.int32))
+        assert np.array_equal(top_s, ref_s.astype(np.float32))
+
+
+def test_graph_replays_match_eager_runs(env, uneven):
+    P, Bt = env
+    W, ligs = uneven
+    pocket = W.pockets[0]
+    srch = I.search_for(pocket, W.search)
+    dp = P.DevicePocket(pocket)
+    sub = ligs.subset(np.arange(64))
+    shape = Bt.chunk_shape_for(sub, np.arange(64), 64)
+    graph = Bt.ChunkPipeline(dp, srch, shape, sub.n_types, 16, use_graph=True)
+    eager = Bt.ChunkPipeline(dp, srch, shape, sub.n_types, 16, use_graph=False)
+    for rep in range(3):
+        say(f"graph replay {rep} against an eager run")
+        for pipe in (graph, eager):
+            pipe.reset()
+            pipe.load(sub, sub.ids.astype(np.int32))
+            pipe.run()
+            torch.cuda.synchronize()
+        assert torch.equal(graph.scores, eager.scores) and torch.equal(graph.ids, eager.ids)
+        _ = torch.ones(1000, device="cuda").sum()  # unrelated eager work between replays
+
+
+def test_large_pocket_parity_sample(env, uneven):
+    P, Bt = env
+    W, ligs = uneven
+    pocket = W.pockets[0]  # 64^3: the oracle's grid is cheap enough to build here
+    srch = I.search_for(pocket, W.search)
+    sel = np.r_[np.flatnonzero(ligs.n_atoms >= 80)[:3], np.arange(3)]
+    sub = ligs.subset(sel)
+    say("64^3 pocket: oracle rescoring of 6 ligands incl. 3 with 80-120 atoms")
+    dp = P.DevicePocket(pocket)
+    r = P.screen(dp, P.DeviceLibrary(sub), P.DeviceSearch(srch))
+    torch.cuda.synchronize()
+    G = oracle.build_grids(pocket)
+    check_exact_and_valid(pocket, G, sub, srch, np.arange(sub.n_lig), r.best_score.cpu().numpy().astype(np.float64),
+                          r.best_start.cpu().numpy(), P.steps_numpy(r.best_steps))
+    # 128^3 grid: sampled nodes
+    big = W.pockets[3]
+    gb = P.DevicePocket(big).view().cpu().numpy()
+    rng = np.random.default_rng(1)
+    tijk = np.stack([rng.integers(0, 16, 500)] + [rng.integers(0, 128, 500) for _ in range(3)], 1).astype(np.int32)
+    ref = oracle.grid_nodes(big, tijk)
+    assert np.all(np.abs(gb[tijk[:, 0], tijk[:, 3], tijk[:, 2], tijk[:, 1]] - ref) <= 1e-6 * np.maximum(1, np.abs(ref)))
+
+
+def test_autotuner_writes_a_usable_table(env, uneven, tmp_path):
+    P, Bt = env
+    W, ligs = uneven
+    pocket = W.pockets[0]
+    srch = I.search_for(pocket, W.search)
+    dp = P.DevicePocket(pocket)
+    small = I.Search(srch.quat[:16], srch.trans[:4], srch.n_steps)
+    say("autotune a small sample")
+    Bt.CANDIDATES[:] = [(32, 4), (64, 8)]
+    table = Bt.autotune(dp, ligs.subset(np.arange(0, 800, 20)), small, per_bucket=8)
+    path = Bt.save_table(table, "testarch", pocket.dims, small.n_steps, str(tmp_path / "t.json"))
+    for b, v in table.items():
+        assert (v["starts_per_item"], v["waves_per_block"]) in [(32, 4), (64, 8)]
+        assert Bt.lookup("testarch", pocket.dims, small.n_steps, b, path) == (v["starts_per_item"],
+                                                                               v["waves_per_block"])
