@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--n-lig", type=int, default=None, help="dock only the first N ligands (a subset workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--layout", choices=("xy4", "linear"), default="xy4",
+                    help="grid layout: 16-byte records of the four xy neighbours, or plain [t][z][y][x]")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for the HBM byte counters)")
     ap.add_argument("--prefilter", action="store_true",
@@ -136,8 +138,8 @@ def main():
     ap.add_argument("--pf-epochs", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the library is sharded by "
-              "ligand; see DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the screen has no multi-GPU path (a library would be sharded "
+              "by ligand over independent processes). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -167,7 +169,8 @@ def main():
     pocket = W.pockets[0]
     S, QT, K_TOP = W.search.n_steps, W.search.n_starts, 1000
 
-    dp = P.DevicePocket(pocket)
+    layout = dock.LAYOUT_XY4 if args.layout == "xy4" else dock.LAYOUT_LINEAR
+    dp = P.DevicePocket(pocket, layout=layout)
     lib = P.DeviceLibrary(ligs)
     ds = P.DeviceSearch(W.search)
     scr = P.Screener(dp, lib, ds)
@@ -232,7 +235,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": (W.name if n_lig == W.n_lig else f"first {n_lig} ligands of " + W.name)
                    + "; top-1000",
-                   "n_lig": n_lig, "grid": "96^3x16", "search": "Q256xT32xS256", "top_k": k},
+                   "n_lig": n_lig, "grid": "96^3x16", "grid_layout": args.layout, "search": "Q256xT32xS256",
+                   "top_k": k},
         "poses_per_sec": poses * args.steps / dt,
         "screen_ms": screen_ms,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_NONPACKED / 1e12,

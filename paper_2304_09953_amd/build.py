@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(PKG, "libligate.so")
 INPUTS_LIB = os.path.join(PKG, "inputs", "libligate_inputs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# Packed-FP32 instruction selection is switched off for every HIP source.
+# Packed-FP32 instruction selection is switched off for every HIP source: some packed FP32 forms
+# have given silently wrong results.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-munsafe-fp-atomics", "-I", os.path.join(ROOT, "include"), "-I", CSRC]

@@ -29,6 +29,33 @@ void set_last_error(const char *fmt, ...);
 int check_launch(const char *what);
 
 // ---------------------------------------------------------------------------------------------
+// Grid storage
+// ---------------------------------------------------------------------------------------------
+
+// DOCK_LAYOUT_XY4 storage order: the 16-byte records are grouped in bricks of 2 x 2 x 2 records,
+// one 128-byte cache line each.  Brick (bx, by, bz) has index bx + nbx (by + nby bz); record
+// (x, y, z) sits at position (x & 1) + 2 (y & 1) + 4 (z & 1) inside its brick.  A trilinear lookup
+// reads the records (x0, y0, z0) and (x0, y0, z0 + 1), usually from the same line, and the lookups
+// of neighbouring points share lines in all three directions.
+struct Xy4Geom {
+    uint32_t nbx, nby, nbz;  // bricks per axis, ceil(n / 2)
+
+    __host__ __device__ static Xy4Geom of(int nx, int ny, int nz) {
+        return Xy4Geom{(uint32_t)(nx + 1) / 2, (uint32_t)(ny + 1) / 2, (uint32_t)(nz + 1) / 2};
+    }
+    __host__ __device__ uint64_t type_bytes() const { return 128ull * nbx * nby * nbz; }
+    __host__ __device__ uint32_t offset(uint32_t x, uint32_t y, uint32_t z) const {
+        return 128u * ((x >> 1) + nbx * ((y >> 1) + nby * (z >> 1))) + 16u * ((x & 1u) + 2u * (y & 1u) + 4u * (z & 1u));
+    }
+};
+
+// Bytes of one type grid in layout g->layout (the descriptor is assumed valid).
+inline uint64_t grid_type_bytes(const dock_grid_desc *g) {
+    if (g->layout == DOCK_LAYOUT_XY4) return Xy4Geom::of(g->nx, g->ny, g->nz).type_bytes();
+    return 4ull * (uint64_t)g->nx * (uint64_t)g->ny * (uint64_t)g->nz;
+}
+
+// ---------------------------------------------------------------------------------------------
 // Packed ligand library (device-resident, opaque to callers)
 // ---------------------------------------------------------------------------------------------
 

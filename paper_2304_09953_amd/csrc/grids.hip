@@ -1,5 +1,6 @@
 // Receptor grid build: one thread per (atom type, node), FP64 sum over the protein atoms,
-// capped, stored in FP32 as [t][z][y][x].
+// capped, stored in FP32 as [t][z][y][x] (linear layout) or scattered into the four xy4 records
+// that hold the node (xy4 layout, bricked record order).
 #include "common.h"
 
 namespace ligate {
@@ -14,7 +15,7 @@ __global__ __launch_bounds__(kGridBlock) void k_build_grids(int nx, int ny, int 
                                                           float oz, float h, const float *__restrict__ prot,
                                                           const int32_t *__restrict__ ptype, int n_prot,
                                                           TypeTable tt, double cap, double r_min, double ck,
-                                                          float *__restrict__ out) {
+                                                          int layout, float *__restrict__ out) {
     __shared__ double sx[kGridBlock], sy[kGridBlock], sz[kGridBlock];
     __shared__ int st[kGridBlock];
     __shared__ double r0t[DOCK_MAX_TYPES], epst[DOCK_MAX_TYPES], qqt[DOCK_MAX_TYPES];
@@ -49,7 +50,22 @@ __global__ __launch_bounds__(kGridBlock) void k_build_grids(int nx, int ny, int 
             sum += epst[tb] * (s6 * s6 - 2.0 * s6) + qqt[tb] * inv;
         }
     }
-    if (node < nxyz) out[(int64_t)t * nxyz + node] = (float)fmin(sum, cap);
+    if (node >= nxyz) return;
+    const float v = (float)fmin(sum, cap);
+    if (layout == DOCK_LAYOUT_LINEAR) {
+        out[(int64_t)t * nxyz + node] = v;
+        return;
+    }
+    // record (X, Y, k) holds nodes (X, Y), (X+1, Y), (X, Y+1), (X+1, Y+1) of plane k, indices
+    // modulo n: node (i, j) is component 0 of record (i, j), 1 of (i-1, j), 2 of (i, j-1), 3 of
+    // (i-1, j-1)
+    const Xy4Geom geo = Xy4Geom::of(nx, ny, nz);
+    const uint32_t im = i == 0 ? nx - 1 : i - 1, jm = j == 0 ? ny - 1 : j - 1;
+    float *base = out + (size_t)t * (geo.type_bytes() / 4);
+    base[geo.offset(i, j, k) / 4 + 0] = v;
+    base[geo.offset(im, j, k) / 4 + 1] = v;
+    base[geo.offset(i, jm, k) / 4 + 2] = v;
+    base[geo.offset(im, jm, k) / 4 + 3] = v;
 }
 
 static int check_desc(const dock_grid_desc *g) {
@@ -58,7 +74,13 @@ static int check_desc(const dock_grid_desc *g) {
     LIGATE_REQUIRE((int64_t)g->nx * g->ny * g->nz < (1ll << 24), DOCK_ERR_LIMIT, "grid has >= 2^24 nodes");
     LIGATE_REQUIRE(g->n_types >= 1 && g->n_types <= DOCK_MAX_TYPES, DOCK_ERR_LIMIT, "n_types must be in [1, 32]");
     LIGATE_REQUIRE(g->spacing > 0.0f, DOCK_ERR_INVALID_ARG, "spacing must be > 0");
-    LIGATE_REQUIRE(g->layout == DOCK_LAYOUT_LINEAR, DOCK_ERR_INVALID_ARG, "unknown grid layout %d", g->layout);
+    LIGATE_REQUIRE(g->layout == DOCK_LAYOUT_LINEAR || g->layout == DOCK_LAYOUT_XY4, DOCK_ERR_INVALID_ARG,
+                   "unknown grid layout %d", g->layout);
+    // one buffer resource addresses all type grids with 31-bit offsets; offsets inside one xy4
+    // type grid are formed in FP32, exact below 2^28 for multiples of 16
+    LIGATE_REQUIRE(grid_type_bytes(g) * (uint64_t)g->n_types < (1ull << 31), DOCK_ERR_LIMIT,
+                   "grids of all types reach 2^31 bytes");
+    LIGATE_REQUIRE(grid_type_bytes(g) < (1ull << 28), DOCK_ERR_LIMIT, "one type grid reaches 2^28 bytes");
     LIGATE_REQUIRE(g->boundary == DOCK_BOUNDARY_CLAMP || g->boundary == DOCK_BOUNDARY_PERIODIC,
                    DOCK_ERR_INVALID_ARG, "unknown boundary mode %d", g->boundary);
     return DOCK_OK;
@@ -74,7 +96,7 @@ extern "C" int dock_grid_bytes(const dock_grid_desc *g, size_t *bytes) {
     int rc = check_desc(g);
     if (rc) return rc;
     LIGATE_REQUIRE(bytes != nullptr, DOCK_ERR_INVALID_ARG, "bytes is NULL");
-    *bytes = sizeof(float) * (size_t)g->n_types * g->nx * g->ny * g->nz;
+    *bytes = (size_t)(grid_type_bytes(g) * (uint64_t)g->n_types);
     return DOCK_OK;
 }
 
@@ -99,6 +121,6 @@ extern "C" int dock_build_grids(const dock_grid_desc *g, const float *d_prot_xyz
     dim3 grid((unsigned)((nxyz + kGridBlock - 1) / kGridBlock), (unsigned)g->n_types);
     hipLaunchKernelGGL(k_build_grids, grid, dim3(kGridBlock), 0, (hipStream_t)stream, g->nx, g->ny, g->nz,
                        g->n_types, g->origin[0], g->origin[1], g->origin[2], g->spacing, d_prot_xyz, d_prot_type,
-                       n_prot, tt, pot->cap, pot->r_min, pot->coulomb_k, d_grids);
+                       n_prot, tt, pot->cap, pot->r_min, pot->coulomb_k, g->layout, d_grids);
     return check_launch("dock_build_grids");
 }

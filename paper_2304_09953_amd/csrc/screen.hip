@@ -34,9 +34,18 @@ int grid_desc_check(const dock_grid_desc *g);
 struct GridC {
     const float *G;
     uint32_t total_bytes;      // all type grids
+    uint32_t type_bytes;       // one type grid
     int nx, ny, nz;
-    uint32_t nx4, nxy4;        // byte strides of y and z
-    float fnx4, fnxy4;         // the same as floats; offsets below 2^26 are exact in FP32
+    // linear layout: byte strides of y and z, also as floats (offsets inside one type grid are
+    // below 2^26 and multiples of 4, so exact in FP32)
+    uint32_t row, plane;
+    float frow, fplane;
+    // xy4 layout: the record offset is 16 x + 32 y + 64 z + kx (x >> 1) + ky (y >> 1) + kz (z >> 1)
+    // (exact in FP32: multiples of 16 below 2^28); the z + 1 record is 64 bytes further for even z
+    // and dz_odd further for odd z
+    Xy4Geom geo;
+    float kx, ky, kz;
+    uint32_t dz_odd;
     float mx, my, mz;          // n - 1: clamp bound
     float cx, cy, cz;          // n - 2: last cell
     float inv_h, ox_h, oy_h, oz_h;  // grid units: u = x / h - o / h
@@ -107,12 +116,13 @@ __device__ __forceinline__ float trilerp(float fx, float fy, float fz, float2 a,
     return fmaf(fz, c1 - c0, c0);
 }
 
-// Cell byte offset and fractions of grid point u.  INSIDE: the caller guarantees
+// Cell byte offset and fractions of grid point u; dz receives the distance in bytes from the
+// (x0, y0, z0) record to the (x0, y0, z0 + 1) record (xy4 layout).  INSIDE: the caller guarantees
 // 0 <= u <= n - 1 - margin, where clamping is the identity and the restraint vanishes, so both
 // variants give the same value there.
-template <bool INSIDE>
+template <bool INSIDE, int LAYOUT>
 __device__ __forceinline__ uint32_t cell(const GridC &g, float ux, float uy, float uz, float &fx, float &fy, float &fz,
-                                         float &rest) {
+                                         float &rest, uint32_t &dz) {
     float qx = ux, qy = uy, qz = uz, x0, y0, z0;
     if constexpr (INSIDE) {
         x0 = floorf(qx);
@@ -133,42 +143,87 @@ __device__ __forceinline__ uint32_t cell(const GridC &g, float ux, float uy, flo
     fx = qx - x0;
     fy = qy - y0;
     fz = qz - z0;
-    return (uint32_t)fmaf(z0, g.fnxy4, fmaf(y0, g.fnx4, 4.0f * x0));
+    if constexpr (LAYOUT == DOCK_LAYOUT_XY4) {
+        const float bx = floorf(0.5f * x0), by = floorf(0.5f * y0), bz = floorf(0.5f * z0);
+        dz = z0 != 2.0f * bz ? g.dz_odd : 64u;
+        return (uint32_t)fmaf(x0, 16.0f, fmaf(bx, g.kx, fmaf(y0, 32.0f, fmaf(by, g.ky, fmaf(z0, 64.0f, bz * g.kz)))));
+    } else {
+        dz = g.plane;
+        return (uint32_t)fmaf(z0, g.fplane, fmaf(y0, g.frow, 4.0f * x0));
+    }
+}
+
+__device__ __forceinline__ float4 ld4(rsrc_t rs, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, 0));
+}
+
+// The four x pairs of a cell whose base node is at byte offset `off` (+ soff): linear layout,
+// one 8-byte load per (y, z) row; xy4 layout, one 16-byte record per z plane, the second `dz`
+// bytes after the first.
+struct CellVals {
+    float2 a, b, c, d;
+};
+
+template <int LAYOUT>
+__device__ __forceinline__ CellVals load_cell(const GridC &g, rsrc_t rs, uint32_t off, uint32_t dz, uint32_t soff) {
+    CellVals v;
+    if constexpr (LAYOUT == DOCK_LAYOUT_XY4) {
+        const float4 r0 = ld4(rs, off, soff), r1 = ld4(rs, off + dz, soff);
+        v.a = make_float2(r0.x, r0.y);
+        v.b = make_float2(r0.z, r0.w);
+        v.c = make_float2(r1.x, r1.y);
+        v.d = make_float2(r1.z, r1.w);
+    } else {
+        v.a = ld2(rs, off, soff);
+        v.b = ld2(rs, off, soff + g.row);
+        v.c = ld2(rs, off, soff + g.plane);
+        v.d = ld2(rs, off, soff + g.plane + g.row);
+    }
+    return v;
 }
 
 // N clamp-mode lookups whose type offsets are wave-uniform (sof, SGPRs); all N cells' loads are
 // issued before any is consumed.
-template <int N, bool INSIDE>
+template <int N, bool INSIDE, int LAYOUT>
 __device__ __forceinline__ void lookup_group(const GridC &g, rsrc_t rs, const uint32_t (&sof)[N], const float (&ux)[N],
                                              const float (&uy)[N], const float (&uz)[N], float (&out)[N]) {
-    uint32_t off[N];
+    uint32_t off[N], dz[N];
     float fx[N], fy[N], fz[N], rest[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) off[k] = cell<INSIDE>(g, ux[k], uy[k], uz[k], fx[k], fy[k], fz[k], rest[k]);
-    float2 a[N], b[N], c[N], d[N];
+    for (int k = 0; k < N; ++k)
+        off[k] = cell<INSIDE, LAYOUT>(g, ux[k], uy[k], uz[k], fx[k], fy[k], fz[k], rest[k], dz[k]);
+    CellVals cv[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) cv[k] = load_cell<LAYOUT>(g, rs, off[k], dz[k], sof[k]);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        a[k] = ld2(rs, off[k], sof[k]);
-        b[k] = ld2(rs, off[k], sof[k] + g.nx4);
-        c[k] = ld2(rs, off[k], sof[k] + g.nxy4);
-        d[k] = ld2(rs, off[k], sof[k] + g.nxy4 + g.nx4);
-    }
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const float v = trilerp(fx[k], fy[k], fz[k], a[k], b[k], c[k], d[k]);
+        const float v = trilerp(fx[k], fy[k], fz[k], cv[k].a, cv[k].b, cv[k].c, cv[k].d);
         out[k] = INSIDE ? v : fmaf(g.w_h2, rest[k], v);
     }
 }
 
 // One lookup whose type offset differs between lanes (rigid placement, pose scoring).
-template <int BOUNDARY>
+template <int BOUNDARY, int LAYOUT>
 __device__ __forceinline__ float lookup_lane(const GridC &g, rsrc_t rs, uint32_t tof, float ux, float uy, float uz) {
     if constexpr (BOUNDARY == DOCK_BOUNDARY_CLAMP) {
         float fx, fy, fz, rest;
-        const uint32_t off = cell<false>(g, ux, uy, uz, fx, fy, fz, rest) + tof;
-        const float2 a = ld2(rs, off, 0), b = ld2(rs, off, g.nx4), c = ld2(rs, off, g.nxy4),
-                     d = ld2(rs, off, g.nxy4 + g.nx4);
-        return fmaf(g.w_h2, rest, trilerp(fx, fy, fz, a, b, c, d));
+        uint32_t dz;
+        const uint32_t off = cell<false, LAYOUT>(g, ux, uy, uz, fx, fy, fz, rest, dz) + tof;
+        const CellVals v = load_cell<LAYOUT>(g, rs, off, dz, 0);
+        return fmaf(g.w_h2, rest, trilerp(fx, fy, fz, v.a, v.b, v.c, v.d));
+    } else if constexpr (LAYOUT == DOCK_LAYOUT_XY4) {
+        // records wrap in x and y; the z neighbour is the record of plane jz
+        const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
+        const float fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
+        int ix = (int)fx0 % g.nx, iy = (int)fy0 % g.ny, iz = (int)fz0 % g.nz;
+        ix += ix < 0 ? g.nx : 0;
+        iy += iy < 0 ? g.ny : 0;
+        iz += iz < 0 ? g.nz : 0;
+        const int jz = iz + 1 == g.nz ? 0 : iz + 1;
+        const float4 r0 = ld4(rs, tof + g.geo.offset(ix, iy, iz), 0);
+        const float4 r1 = ld4(rs, tof + g.geo.offset(ix, iy, jz), 0);
+        return trilerp(fx, fy, fz, make_float2(r0.x, r0.y), make_float2(r0.z, r0.w), make_float2(r1.x, r1.y),
+                       make_float2(r1.z, r1.w));
     } else {
         const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
         const float fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
@@ -204,7 +259,7 @@ __device__ void load_ligand(LigLDS &L, const PackView &pk, int lig, const GridC 
         L.lig = lig;
     }
     if (d.status != DOCK_LIG_OK) return;
-    const uint32_t tbytes = 4u * (uint32_t)g.nx * (uint32_t)g.ny * (uint32_t)g.nz;
+    const uint32_t tbytes = g.type_bytes;
     for (int i = tid; i < d.n; i += nthreads) {
         L.xr[i] = pk.x[d.atom_off + i] * g.inv_h;
         L.yr[i] = pk.y[d.atom_off + i] * g.inv_h;
@@ -313,7 +368,7 @@ __device__ __forceinline__ void axis(const TorRec &tr, const float (&cx)[2], con
 }
 
 // Score of the conformer in registers from scratch: every atom's grid term and every clash pair.
-template <int BOUNDARY>
+template <int BOUNDARY, int LAYOUT>
 __device__ float direct_score(const GridC &g, rsrc_t rs, const SearchC &s, const LigLDS &L, const float (&cx)[2],
                               const float (&cy)[2], const float (&cz)[2]) {
     const int lane = lane_id();
@@ -322,7 +377,7 @@ __device__ float direct_score(const GridC &g, rsrc_t rs, const SearchC &s, const
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int i = lane + kWave * h;
-        if (i < n) acc += lookup_lane<BOUNDARY>(g, rs, L.tof[i], cx[h], cy[h], cz[h]);
+        if (i < n) acc += lookup_lane<BOUNDARY, LAYOUT>(g, rs, L.tof[i], cx[h], cy[h], cz[h]);
     }
     for (int i = 0; i < n; ++i) {
         const float xi = __shfl(i < kWave ? cx[0] : cx[1], i & 63);
@@ -345,7 +400,7 @@ __device__ float direct_score(const GridC &g, rsrc_t rs, const SearchC &s, const
 
 // One greedy pass from rigid start p.  Returns the final score (identical on all lanes);
 // lane k (< B) receives the step chosen for torsion k in `my_step`.
-template <int APL, int BOUNDARY>
+template <int APL, int BOUNDARY, int LAYOUT>
 __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const LigLDS &L, WaveLDS &W, int p,
                            float clash_ref, const float (&cs)[APL], const float (&sn)[APL], int &my_step) {
     const int lane = lane_id();
@@ -356,7 +411,7 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int i = lane + kWave * h;
-        if (i < n) eg += lookup_lane<BOUNDARY>(g, rs, L.tof[i], cx[h], cy[h], cz[h]);
+        if (i < n) eg += lookup_lane<BOUNDARY, LAYOUT>(g, rs, L.tof[i], cx[h], cy[h], cz[h]);
     }
     float E = wave_sum(eg) + clash_ref;
     // The score is carried incrementally in FP32; when it passed through values much larger than
@@ -446,7 +501,7 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
                         }
                     if constexpr (BOUNDARY == DOCK_BOUNDARY_CLAMP) {
                         if (all_inside) {
-                            lookup_group<4, true>(g, rs, so, gx, gy, gz, v);
+                            lookup_group<4, true, LAYOUT>(g, rs, so, gx, gy, gz, v);
                         } else {  // the clamp path needs more registers: two groups of two
 #pragma unroll
                             for (int hh = 0; hh < 4; hh += 2) {
@@ -454,14 +509,14 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
                                 const float gx2[2] = {gx[hh], gx[hh + 1]}, gy2[2] = {gy[hh], gy[hh + 1]},
                                             gz2[2] = {gz[hh], gz[hh + 1]};
                                 float v2[2];
-                                lookup_group<2, false>(g, rs, so2, gx2, gy2, gz2, v2);
+                                lookup_group<2, false, LAYOUT>(g, rs, so2, gx2, gy2, gz2, v2);
                                 v[hh] = v2[0];
                                 v[hh + 1] = v2[1];
                             }
                         }
                     } else {
 #pragma unroll
-                        for (int idx = 0; idx < 4; ++idx) v[idx] = lookup_lane<BOUNDARY>(g, rs, so[idx], gx[idx], gy[idx], gz[idx]);
+                        for (int idx = 0; idx < 4; ++idx) v[idx] = lookup_lane<BOUNDARY, LAYOUT>(g, rs, so[idx], gx[idx], gy[idx], gz[idx]);
                     }
 #pragma unroll
                     for (int a = 0; a < NA; ++a)
@@ -551,7 +606,7 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
         }
         if (lane == k) my_step = sbest;
     }
-    if (Emax > 16.0f * fmaxf(1.0f, fabsf(E))) E = direct_score<BOUNDARY>(g, rs, s, L, cx, cy, cz);
+    if (Emax > 16.0f * fmaxf(1.0f, fabsf(E))) E = direct_score<BOUNDARY, LAYOUT>(g, rs, s, L, cx, cy, cz);
     return E;
 }
 
@@ -605,7 +660,7 @@ __global__ void k_screen_plan(const LigDesc *desc, int n_lig, int S, uint64_t *k
     }
 }
 
-template <int APL, int BOUNDARY>
+template <int APL, int BOUNDARY, int LAYOUT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_screen(ScreenArgs A) {
     extern __shared__ __align__(16) char smem[];
     LigLDS &L = *reinterpret_cast<LigLDS *>(smem);
@@ -633,7 +688,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             const int p0 = batch * A.P, p1 = min(p0 + A.P, A.s.QT);
             for (int p = p0 + w; p < p1; p += A.nw) {
                 int step = 0;
-                const float E = run_start<APL, BOUNDARY>(A.g, rs, A.s, L, W, p, clash_ref, cs, sn, step);
+                const float E = run_start<APL, BOUNDARY, LAYOUT>(A.g, rs, A.s, L, W, p, clash_ref, cs, sn, step);
                 const uint64_t key = ((uint64_t)float_to_ordered(E) << 32) | (uint32_t)p;
                 wbest = key < wbest ? key : wbest;
                 if (A.start_scores && lane == 0) A.start_scores[(size_t)lig * A.s.QT + p] = E;
@@ -654,7 +709,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 // Reruns each ligand's winning start to recover its torsion steps, then writes the outputs.
-template <int APL, int BOUNDARY>
+template <int APL, int BOUNDARY, int LAYOUT>
 __global__ __launch_bounds__(64) void k_replay(ScreenArgs A, float *best_score, int32_t *best_start,
                                                uint16_t *best_steps) {
     extern __shared__ __align__(16) char smem[];
@@ -673,7 +728,7 @@ __global__ __launch_bounds__(64) void k_replay(ScreenArgs A, float *best_score, 
     if (L.status == DOCK_LIG_OK && key != ~0ull) {
         p = (int)(uint32_t)key;
         const float clash_ref = rigid_clash(L, A.s);
-        E = run_start<APL, BOUNDARY>(A.g, rs, A.s, L, W, p, clash_ref, cs, sn, step);
+        E = run_start<APL, BOUNDARY, LAYOUT>(A.g, rs, A.s, L, W, p, clash_ref, cs, sn, step);
     }
     if (lane < DOCK_MAX_TORSIONS) best_steps[(size_t)lig * DOCK_MAX_TORSIONS + lane] =
         (uint16_t)(p >= 0 && lane < L.B ? step : 0);
@@ -684,7 +739,7 @@ __global__ __launch_bounds__(64) void k_replay(ScreenArgs A, float *best_score, 
 }
 
 // Scores explicit poses from scratch: place, apply the given steps, full grid + clash sum.
-template <int BOUNDARY>
+template <int BOUNDARY, int LAYOUT>
 __global__ __launch_bounds__(64) void k_score_poses(GridC g, SearchC s, PackView pk, int n_lig, const int32_t *d_lig,
                                                     const int32_t *d_start, const uint16_t *d_steps, int64_t n_poses,
                                                     float *out) {
@@ -728,7 +783,7 @@ __global__ __launch_bounds__(64) void k_score_poses(GridC g, SearchC s, PackView
         }
     }
     // every atom's grid term and every clash pair, from the final coordinates
-    const float acc = direct_score<BOUNDARY>(g, rs, s, L, cx, cy, cz);
+    const float acc = direct_score<BOUNDARY, LAYOUT>(g, rs, s, L, cx, cy, cz);
     if (lane == 0) out[pose] = acc;
 }
 
@@ -742,11 +797,17 @@ static GridC make_grid(const dock_grid_desc *d, const float *G) {
     g.nx = d->nx;
     g.ny = d->ny;
     g.nz = d->nz;
-    g.total_bytes = 4u * (uint32_t)d->n_types * (uint32_t)(d->nx * d->ny * d->nz);
-    g.nx4 = 4u * (uint32_t)d->nx;
-    g.nxy4 = 4u * (uint32_t)(d->nx * d->ny);
-    g.fnx4 = (float)g.nx4;
-    g.fnxy4 = (float)g.nxy4;
+    g.type_bytes = (uint32_t)grid_type_bytes(d);
+    g.total_bytes = g.type_bytes * (uint32_t)d->n_types;
+    g.row = 4u * (uint32_t)d->nx;
+    g.plane = 4u * (uint32_t)(d->nx * d->ny);
+    g.frow = (float)g.row;
+    g.fplane = (float)g.plane;
+    g.geo = Xy4Geom::of(d->nx, d->ny, d->nz);
+    g.kx = 96.0f;
+    g.ky = 128.0f * (float)g.geo.nbx - 64.0f;
+    g.kz = 128.0f * (float)g.geo.nbx * (float)g.geo.nby - 128.0f;
+    g.dz_odd = 128u * g.geo.nbx * g.geo.nby - 64u;
     g.inv_h = 1.0f / d->spacing;
     g.ox_h = d->origin[0] / d->spacing;
     g.oy_h = d->origin[1] / d->spacing;
@@ -794,7 +855,7 @@ static size_t al(size_t v) { return (v + 255) & ~size_t(255); }
 
 static size_t screen_lds(int nw) { return ((sizeof(LigLDS) + 15) & ~size_t(15)) + sizeof(WaveLDS) * (size_t)nw; }
 
-template <int APL, int BOUNDARY>
+template <int APL, int BOUNDARY, int LAYOUT>
 static int launch_screen(const ScreenArgs &A, float *bs, int32_t *bp, uint16_t *bst, hipStream_t st) {
     static int cu = 0;
     if (cu == 0) {
@@ -805,24 +866,31 @@ static int launch_screen(const ScreenArgs &A, float *bs, int32_t *bp, uint16_t *
     }
     const size_t lds = screen_lds(A.nw);
     int per_cu = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_screen<APL, BOUNDARY>),
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_screen<APL, BOUNDARY, LAYOUT>),
                                                  kWave * A.nw, lds);
     if (per_cu <= 0) per_cu = 1;
     const int64_t blocks = std::min<int64_t>(A.n_items, (int64_t)cu * per_cu);
     if (blocks > 0)
-        hipLaunchKernelGGL((k_screen<APL, BOUNDARY>), dim3((unsigned)blocks), dim3(kWave * A.nw), lds, st, A);
-    hipLaunchKernelGGL((k_replay<APL, BOUNDARY>), dim3((unsigned)A.n_lig), dim3(kWave), screen_lds(1), st, A, bs, bp,
+        hipLaunchKernelGGL((k_screen<APL, BOUNDARY, LAYOUT>), dim3((unsigned)blocks), dim3(kWave * A.nw), lds, st, A);
+    hipLaunchKernelGGL((k_replay<APL, BOUNDARY, LAYOUT>), dim3((unsigned)A.n_lig), dim3(kWave), screen_lds(1), st, A, bs, bp,
                        bst);
     return check_launch("dock_screen");
 }
 
-template <int BOUNDARY>
+template <int BOUNDARY, int LAYOUT>
 static int dispatch_apl(int S, const ScreenArgs &A, float *bs, int32_t *bp, uint16_t *bst, hipStream_t st) {
-    if (S <= 64) return launch_screen<1, BOUNDARY>(A, bs, bp, bst, st);
-    if (S <= 128) return launch_screen<2, BOUNDARY>(A, bs, bp, bst, st);
-    if (S <= 256) return launch_screen<4, BOUNDARY>(A, bs, bp, bst, st);
-    if (S <= 512) return launch_screen<8, BOUNDARY>(A, bs, bp, bst, st);
-    return launch_screen<16, BOUNDARY>(A, bs, bp, bst, st);
+    if (S <= 64) return launch_screen<1, BOUNDARY, LAYOUT>(A, bs, bp, bst, st);
+    if (S <= 128) return launch_screen<2, BOUNDARY, LAYOUT>(A, bs, bp, bst, st);
+    if (S <= 256) return launch_screen<4, BOUNDARY, LAYOUT>(A, bs, bp, bst, st);
+    if (S <= 512) return launch_screen<8, BOUNDARY, LAYOUT>(A, bs, bp, bst, st);
+    return launch_screen<16, BOUNDARY, LAYOUT>(A, bs, bp, bst, st);
+}
+
+template <int LAYOUT>
+static int dispatch_boundary(int boundary, int S, const ScreenArgs &A, float *bs, int32_t *bp, uint16_t *bst,
+                             hipStream_t st) {
+    if (boundary == DOCK_BOUNDARY_PERIODIC) return dispatch_apl<DOCK_BOUNDARY_PERIODIC, LAYOUT>(S, A, bs, bp, bst, st);
+    return dispatch_apl<DOCK_BOUNDARY_CLAMP, LAYOUT>(S, A, bs, bp, bst, st);
 }
 
 static int default_cu_count() {
@@ -897,9 +965,9 @@ extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const
                        A.s.QT);
     rc = radix_sort_u64(order, n_lig, 32, 64, rws, st);
     if (rc) return rc;
-    if (gd->boundary == DOCK_BOUNDARY_PERIODIC)
-        return dispatch_apl<DOCK_BOUNDARY_PERIODIC>(A.s.S, A, d_best_score, d_best_start, d_best_steps, st);
-    return dispatch_apl<DOCK_BOUNDARY_CLAMP>(A.s.S, A, d_best_score, d_best_start, d_best_steps, st);
+    if (gd->layout == DOCK_LAYOUT_XY4)
+        return dispatch_boundary<DOCK_LAYOUT_XY4>(gd->boundary, A.s.S, A, d_best_score, d_best_start, d_best_steps, st);
+    return dispatch_boundary<DOCK_LAYOUT_LINEAR>(gd->boundary, A.s.S, A, d_best_score, d_best_start, d_best_steps, st);
 }
 
 extern "C" int dock_score_poses(const dock_grid_desc *gd, const float *d_grids, const void *d_pack, int32_t n_lig,
@@ -917,11 +985,19 @@ extern "C" int dock_score_poses(const dock_grid_desc *gd, const float *d_grids, 
     const SearchC s = make_search(sd, gd->spacing);
     const PackView pk = PackView::of(d_pack, n_lig, n_atoms_total);
     hipStream_t st = (hipStream_t)stream;
-    if (gd->boundary == DOCK_BOUNDARY_PERIODIC)
-        hipLaunchKernelGGL(k_score_poses<DOCK_BOUNDARY_PERIODIC>, dim3((unsigned)n_poses), dim3(kWave), 0, st, g, s,
-                           pk, n_lig, d_lig, d_start, d_steps, n_poses, d_scores);
+    const dim3 grid((unsigned)n_poses), block(kWave);
+    const bool per = gd->boundary == DOCK_BOUNDARY_PERIODIC, xy4 = gd->layout == DOCK_LAYOUT_XY4;
+    if (per && xy4)
+        hipLaunchKernelGGL((k_score_poses<DOCK_BOUNDARY_PERIODIC, DOCK_LAYOUT_XY4>), grid, block, 0, st, g, s, pk,
+                           n_lig, d_lig, d_start, d_steps, n_poses, d_scores);
+    else if (per)
+        hipLaunchKernelGGL((k_score_poses<DOCK_BOUNDARY_PERIODIC, DOCK_LAYOUT_LINEAR>), grid, block, 0, st, g, s, pk,
+                           n_lig, d_lig, d_start, d_steps, n_poses, d_scores);
+    else if (xy4)
+        hipLaunchKernelGGL((k_score_poses<DOCK_BOUNDARY_CLAMP, DOCK_LAYOUT_XY4>), grid, block, 0, st, g, s, pk, n_lig,
+                           d_lig, d_start, d_steps, n_poses, d_scores);
     else
-        hipLaunchKernelGGL(k_score_poses<DOCK_BOUNDARY_CLAMP>, dim3((unsigned)n_poses), dim3(kWave), 0, st, g, s, pk,
+        hipLaunchKernelGGL((k_score_poses<DOCK_BOUNDARY_CLAMP, DOCK_LAYOUT_LINEAR>), grid, block, 0, st, g, s, pk,
                            n_lig, d_lig, d_start, d_steps, n_poses, d_scores);
     return check_launch("dock_score_poses");
 }

@@ -20,6 +20,7 @@ MAX_TORSIONS = 16
 MAX_TYPES = 32
 MAX_STEPS = 1024
 LAYOUT_LINEAR = 0
+LAYOUT_XY4 = 1
 BOUNDARY_CLAMP = 0
 BOUNDARY_PERIODIC = 1
 
@@ -104,10 +105,10 @@ def _stream(stream=None):
 # Descriptors
 # ------------------------------------------------------------------------------------------------
 
-def grid_desc(pocket, boundary: int = BOUNDARY_CLAMP) -> GridDesc:
+def grid_desc(pocket, boundary: int = BOUNDARY_CLAMP, layout: int = LAYOUT_XY4) -> GridDesc:
     nx, ny, nz = pocket.dims
     return GridDesc(nx, ny, nz, pocket.n_types, (ctypes.c_float * 3)(*[float(v) for v in pocket.origin]),
-                    float(pocket.spacing), LAYOUT_LINEAR, boundary, float(pocket.w_out))
+                    float(pocket.spacing), layout, boundary, float(pocket.w_out))
 
 
 def search_desc(d_quat: torch.Tensor, d_trans: torch.Tensor, n_steps: int, clash_cut: float = 2.5,

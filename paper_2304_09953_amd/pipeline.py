@@ -23,9 +23,11 @@ def _dev(a, device, dtype=None):
 class DevicePocket:
     """Receptor grids built on the device by ``dock_build_grids``."""
 
-    def __init__(self, pocket, device="cuda", boundary: int = dock.BOUNDARY_CLAMP, stream=None):
+    def __init__(self, pocket, device="cuda", boundary: int = dock.BOUNDARY_CLAMP, layout: int = dock.LAYOUT_XY4,
+                 stream=None):
         self.pocket = pocket
-        self.desc = dock.grid_desc(pocket, boundary)
+        self.layout = layout
+        self.desc = dock.grid_desc(pocket, boundary, layout)
         nbytes = dock.grid_bytes(self.desc)
         self.grids = torch.empty(nbytes // 4, dtype=torch.float32, device=device)
         self.prot_xyz = _dev(pocket.prot_xyz, device, torch.float32)
@@ -34,8 +36,35 @@ class DevicePocket:
                          pocket.cap, pocket.r_min, pocket.coulomb_k, self.grids, stream)
 
     def view(self):
+        """Node values as [t][z][y][x] (in the xy4 layout, component 0 of each record)."""
         nx, ny, nz = self.pocket.dims
+        if self.layout == dock.LAYOUT_XY4:
+            return self.records()[..., 0]
         return self.grids.view(self.pocket.n_types, nz, ny, nx)
+
+    def _bricks(self):
+        nx, ny, nz = self.pocket.dims
+        return (nx + 1) // 2, (ny + 1) // 2, (nz + 1) // 2
+
+    def records(self):
+        """The xy4 records as [t][z][y][x][4] (a copy; storage is in 2 x 2 x 2 bricks of records)."""
+        assert self.layout == dock.LAYOUT_XY4
+        nx, ny, nz = self.pocket.dims
+        bx, by, bz = self._bricks()
+        T = self.pocket.n_types
+        r = self.grids.view(T, bz, by, bx, 2, 2, 2, 4).permute(0, 1, 4, 2, 5, 3, 6, 7)
+        return r.reshape(T, 2 * bz, 2 * by, 2 * bx, 4)[:, :nz, :ny, :nx].contiguous()
+
+    def write_records(self, rec: torch.Tensor):
+        """Stores [t][z][y][x][4] records in brick order (the inverse of records())."""
+        assert self.layout == dock.LAYOUT_XY4
+        nx, ny, nz = self.pocket.dims
+        bx, by, bz = self._bricks()
+        T = self.pocket.n_types
+        full = torch.zeros((T, 2 * bz, 2 * by, 2 * bx, 4), dtype=torch.float32, device=self.grids.device)
+        full[:, :nz, :ny, :nx] = rec
+        b = full.view(T, bz, 2, by, 2, bx, 2, 4).permute(0, 1, 3, 5, 2, 4, 6, 7)
+        self.grids.copy_(b.reshape(-1))
 
 
 class DeviceLibrary:

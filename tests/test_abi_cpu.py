@@ -86,6 +86,16 @@ def test_grid_desc_validation():
         assert lib.dock_last_error() != b""
     assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, n_types=33)), ctypes.byref(out)) == -2
     assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, nx=300, ny=300, nz=300)), ctypes.byref(out)) == -2
+    # xy4 layout: 16-byte records in 128-byte bricks of 2 x 2 x 2, dims rounded up to even;
+    # all type grids below 2^31 bytes, one type grid below 2^28
+    assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, layout=1)), ctypes.byref(out)) == 0
+    assert out.value == 128 * (4 * 5 * 5) * 4
+    odd = dict(nx=255, ny=255, nz=255, n_types=1)  # < 2^24 nodes, but 128^3 bricks = 2^28 bytes
+    assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, layout=0, **odd)), ctypes.byref(out)) == 0
+    assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, layout=1, **odd)), ctypes.byref(out)) == -2
+    big = dict(nx=200, ny=200, nz=200, n_types=17)  # 8e6 nodes x 17 types x 16 B > 2^31
+    assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, layout=0, **big)), ctypes.byref(out)) == 0
+    assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, layout=1, **big)), ctypes.byref(out)) == -2
 
 
 def test_size_queries_and_argument_errors():

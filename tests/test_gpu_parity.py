@@ -48,6 +48,28 @@ def test_grids_pocket48_match_oracle(p48):
     assert err.max() <= 1e-6
 
 
+def test_xy4_records_hold_the_wrapped_neighbours(P):
+    pocket = I.make_pocket((40, 36, 28), 4, pocket_id=3)
+    say("xy4 records vs the linear grid, 40x36x28 x 4")
+    lin = P.DevicePocket(pocket, layout=0).view()
+    rec = P.DevicePocket(pocket, layout=1).records()
+    # dims of the [t][z][y][x] view: x is 3, y is 2
+    assert torch.equal(rec[..., 0], lin)
+    assert torch.equal(rec[..., 1], torch.roll(lin, -1, dims=3))
+    assert torch.equal(rec[..., 2], torch.roll(lin, -1, dims=2))
+    assert torch.equal(rec[..., 3], torch.roll(lin, (-1, -1), dims=(2, 3)))
+    # storage order: 2 x 2 x 2 bricks of 16-byte records, brick x fastest
+    dp = P.DevicePocket(pocket, layout=1)
+    raw = dp.grids.view(4, 14, 18, 20, 2, 2, 2, 4)
+    # brick (7, 5, 3), position (1, 0, 1): record (x 15, y 10, z 7)
+    assert torch.equal(raw[1, 3, 5, 7, 1, 0, 1],
+                       torch.stack([lin[1, 7, 10, 15], lin[1, 7, 10, 16], lin[1, 7, 11, 15], lin[1, 7, 11, 16]]))
+    back = P.DevicePocket(pocket, layout=1)
+    back.grids.zero_()
+    back.write_records(rec)
+    assert torch.equal(back.grids, dp.grids)
+
+
 def test_grids_96_sampled_nodes(P):
     pocket = I.make_pocket(96, 16)
     say("96^3 x 16 grid build")
@@ -262,13 +284,14 @@ def test_screen_is_deterministic_and_tuning_invariant(P, p48):
             assert np.array_equal(r[key], runs[0][key]), key
 
 
-def test_periodic_boundary_translation_covariance(P):
+@pytest.mark.parametrize("layout", [0, 1])
+def test_periodic_boundary_translation_covariance(P, layout):
     pocket = I.make_pocket(40, 4, pocket_id=11)
     G = oracle.build_grids(pocket)
     ligs = I.make_ligands(16, I.DIST_DRUGLIKE, 4, stream="test")
     srch = I.make_search(4, 3, 16, 3.0, pocket.center)
-    say("periodic boundary: GPU vs oracle and roll covariance")
-    dp = P.DevicePocket(pocket, boundary=1)
+    say(f"periodic boundary, layout {layout}: GPU vs oracle and roll covariance")
+    dp = P.DevicePocket(pocket, boundary=1, layout=layout)
     lib = P.DeviceLibrary(ligs)
     rng = np.random.default_rng(5)
     n = 400
@@ -282,13 +305,34 @@ def test_periodic_boundary_translation_covariance(P):
         shifted = I.Search(srch.quat, srch.trans + np.float32(h * k) * np.eye(3, dtype=np.float32)[axis_d],
                            srch.n_steps)
         moved = P.score_poses(dp, lib, P.DeviceSearch(shifted), lig, start, steps).cpu().numpy()
-        rolled = P.DevicePocket(pocket, boundary=1)
-        rolled.grids.copy_(torch.roll(dp.view(), -k, dims=axis_t).reshape(-1))
+        rolled = P.DevicePocket(pocket, boundary=1, layout=layout)
+        if layout == 1:  # rolling the wrapped xy4 records gives the records of the rolled grid
+            rolled.write_records(torch.roll(dp.records(), -k, dims=axis_t))
+        else:
+            rolled.grids.copy_(torch.roll(dp.view(), -k, dims=axis_t).reshape(-1))
         at_rolled = P.score_poses(rolled, lib, P.DeviceSearch(srch), lig, start, steps).cpu().numpy()
         assert np.all(np.abs(moved - at_rolled) <= tol_pose(at_rolled, ligs.n_atoms[lig]))
     full = I.Search(srch.quat, srch.trans + np.float32(h * 40) * np.ones(3, np.float32), srch.n_steps)
     wrapped = P.score_poses(dp, lib, P.DeviceSearch(full), lig, start, steps).cpu().numpy()
     assert np.all(np.abs(wrapped - base) <= tol_pose(base, ligs.n_atoms[lig]))
+
+
+@pytest.mark.parametrize("boundary", [0, 1])
+def test_layouts_give_identical_screens(P, p48, boundary):
+    W, pocket, _, _, ligs = p48
+    sub = ligs.subset(np.arange(0, 100, 7))
+    runs, poses = [], []
+    rng = np.random.default_rng(2)
+    lig, start = rng.integers(0, sub.n_lig, 300), rng.integers(0, W.search.n_starts, 300)
+    steps = rng.integers(0, W.search.n_steps, (300, 12))
+    for layout in (0, 1):
+        say(f"screen pocket48-lib100 subset, boundary {boundary}, layout {layout}")
+        dp = P.DevicePocket(pocket, boundary=boundary, layout=layout)
+        runs.append(_screen(P, dp, sub, W.search, start_scores=True))
+        poses.append(P.score_poses(dp, P.DeviceLibrary(sub), P.DeviceSearch(W.search), lig, start, steps).cpu())
+    for key in ("score", "start", "steps", "finals", "start_steps"):
+        assert np.array_equal(runs[0][key], runs[1][key]), key
+    assert torch.equal(poses[0], poses[1])
 
 
 # ------------------------------------------------------------------------------------------------
