@@ -59,10 +59,12 @@ extern "C" {
 #define DOCK_MAX_STEPS 1024
 
 #define DOCK_LAYOUT_LINEAR 0     /* grids [t][z][y][x], FP32, x fastest */
-#define DOCK_LAYOUT_XY4 1        /* grids [t][z][y][x][4]: per node the values of the nodes
-                                    (x, y), (x+1, y), (x, y+1), (x+1, y+1) in its z plane, indices
-                                    beyond the last node wrapping to 0; 4x the memory, half the load
-                                    instructions per trilinear lookup */
+#define DOCK_LAYOUT_XY4 1        /* per node a 16-byte record of its z plane: G(x, y),
+                                    G(x+1, y) - G(x, y), G(x, y+1), G(x+1, y+1) - G(x, y+1)
+                                    (differences rounded to FP32; indices beyond the last node wrap
+                                    to 0), stored in bricks of 2 x 2 x 2 records (128 bytes) with
+                                    dimensions rounded up to even; about 4x the memory, and a
+                                    trilinear lookup reads two records, mostly from one line */
 #define DOCK_BOUNDARY_CLAMP 0    /* clamp into the box + w_out * |x - clamp(x)|^2 */
 #define DOCK_BOUNDARY_PERIODIC 1 /* indices wrap modulo the grid size */
 

@@ -1,6 +1,6 @@
 // Receptor grid build: one thread per (atom type, node), FP64 sum over the protein atoms,
 // capped, stored in FP32 as [t][z][y][x] (linear layout) or scattered into the four xy4 records
-// that hold the node (xy4 layout, bricked record order).
+// that hold the node (xy4 layout, bricked record order), whose x differences a second pass forms.
 #include "common.h"
 
 namespace ligate {
@@ -68,6 +68,24 @@ __global__ __launch_bounds__(kGridBlock) void k_build_grids(int nx, int ny, int 
     base[geo.offset(im, jm, k) / 4 + 3] = v;
 }
 
+// xy4 records (a, b, c, d) -> (a, b - a, c, d - c), in FP32 as the interpolation would form them;
+// the padding records of odd dimensions (never read) are set to zero.
+__global__ __launch_bounds__(kGridBlock) void k_xy4_diff(float4 *__restrict__ rec, int64_t n, int nx, int ny, int nz) {
+    const int64_t i = (int64_t)blockIdx.x * kGridBlock + threadIdx.x;
+    if (i >= n) return;
+    const Xy4Geom geo = Xy4Geom::of(nx, ny, nz);
+    const int64_t r_type = (int64_t)(geo.type_bytes() / 16);
+    const uint32_t in_type = (uint32_t)(i % r_type), brick = in_type >> 3, pos = in_type & 7u;
+    const uint32_t x = 2u * (brick % geo.nbx) + (pos & 1u);
+    const uint32_t y = 2u * ((brick / geo.nbx) % geo.nby) + ((pos >> 1) & 1u);
+    const uint32_t z = 2u * (brick / (geo.nbx * geo.nby)) + (pos >> 2);
+    float4 r = rec[i];
+    r.y = r.y - r.x;
+    r.w = r.w - r.z;
+    if (x >= (uint32_t)nx || y >= (uint32_t)ny || z >= (uint32_t)nz) r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    rec[i] = r;
+}
+
 static int check_desc(const dock_grid_desc *g) {
     LIGATE_REQUIRE(g != nullptr, DOCK_ERR_INVALID_ARG, "grid descriptor is NULL");
     LIGATE_REQUIRE(g->nx >= 2 && g->ny >= 2 && g->nz >= 2, DOCK_ERR_INVALID_ARG, "grid dims must be >= 2");
@@ -122,5 +140,10 @@ extern "C" int dock_build_grids(const dock_grid_desc *g, const float *d_prot_xyz
     hipLaunchKernelGGL(k_build_grids, grid, dim3(kGridBlock), 0, (hipStream_t)stream, g->nx, g->ny, g->nz,
                        g->n_types, g->origin[0], g->origin[1], g->origin[2], g->spacing, d_prot_xyz, d_prot_type,
                        n_prot, tt, pot->cap, pot->r_min, pot->coulomb_k, g->layout, d_grids);
+    if (g->layout == DOCK_LAYOUT_XY4) {
+        const int64_t n = (int64_t)(grid_type_bytes(g) / 16) * g->n_types;
+        hipLaunchKernelGGL(k_xy4_diff, dim3((unsigned)((n + kGridBlock - 1) / kGridBlock)), dim3(kGridBlock), 0,
+                           (hipStream_t)stream, reinterpret_cast<float4 *>(d_grids), n, g->nx, g->ny, g->nz);
+    }
     return check_launch("dock_build_grids");
 }

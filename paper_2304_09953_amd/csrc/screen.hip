@@ -85,7 +85,9 @@ constexpr int kSurvCap = 128;
 struct WaveLDS {
     Coef coef[kWave];
     uint8_t atom[kWave];
-    float4 surv[kSurvCap];
+    uint16_t sidx[kSurvCap];      // surviving pair: moving slot q | fixed atom j << 8
+    float4 surv[kSurvCap];        // its distance coefficients (A, C, D)
+    float4 pos[DOCK_MAX_ATOMS];   // current coordinates, written at the start of each sweep
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -112,6 +114,15 @@ __device__ __forceinline__ float ld1(rsrc_t rs, uint32_t voff) {
 __device__ __forceinline__ float trilerp(float fx, float fy, float fz, float2 a, float2 b, float2 c, float2 d) {
     const float c00 = fmaf(fx, a.y - a.x, a.x), c10 = fmaf(fx, b.y - b.x, b.x);
     const float c01 = fmaf(fx, c.y - c.x, c.x), c11 = fmaf(fx, d.y - d.x, d.x);
+    const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
+    return fmaf(fz, c1 - c0, c0);
+}
+
+// The same with the x pairs given as (G(x0), G(x0 + 1) - G(x0)), the difference rounded to FP32
+// exactly as trilerp forms it, so both give identical results.
+__device__ __forceinline__ float trilerp_dx(float fx, float fy, float fz, float2 a, float2 b, float2 c, float2 d) {
+    const float c00 = fmaf(fx, a.y, a.x), c10 = fmaf(fx, b.y, b.x);
+    const float c01 = fmaf(fx, c.y, c.x), c11 = fmaf(fx, d.y, d.x);
     const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
     return fmaf(fz, c1 - c0, c0);
 }
@@ -158,11 +169,17 @@ __device__ __forceinline__ float4 ld4(rsrc_t rs, uint32_t voff, uint32_t soff) {
 }
 
 // The four x pairs of a cell whose base node is at byte offset `off` (+ soff): linear layout,
-// one 8-byte load per (y, z) row; xy4 layout, one 16-byte record per z plane, the second `dz`
-// bytes after the first.
+// one 8-byte load per (y, z) row, as (G(x0), G(x0 + 1)); xy4 layout, one 16-byte record per z
+// plane, the second `dz` bytes after the first, as (G(x0), G(x0 + 1) - G(x0)).
 struct CellVals {
     float2 a, b, c, d;
 };
+
+template <int LAYOUT>
+__device__ __forceinline__ float interp(float fx, float fy, float fz, const CellVals &v) {
+    if constexpr (LAYOUT == DOCK_LAYOUT_XY4) return trilerp_dx(fx, fy, fz, v.a, v.b, v.c, v.d);
+    return trilerp(fx, fy, fz, v.a, v.b, v.c, v.d);
+}
 
 template <int LAYOUT>
 __device__ __forceinline__ CellVals load_cell(const GridC &g, rsrc_t rs, uint32_t off, uint32_t dz, uint32_t soff) {
@@ -197,7 +214,7 @@ __device__ __forceinline__ void lookup_group(const GridC &g, rsrc_t rs, const ui
     for (int k = 0; k < N; ++k) cv[k] = load_cell<LAYOUT>(g, rs, off[k], dz[k], sof[k]);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const float v = trilerp(fx[k], fy[k], fz[k], cv[k].a, cv[k].b, cv[k].c, cv[k].d);
+        const float v = interp<LAYOUT>(fx[k], fy[k], fz[k], cv[k]);
         out[k] = INSIDE ? v : fmaf(g.w_h2, rest[k], v);
     }
 }
@@ -210,7 +227,7 @@ __device__ __forceinline__ float lookup_lane(const GridC &g, rsrc_t rs, uint32_t
         uint32_t dz;
         const uint32_t off = cell<false, LAYOUT>(g, ux, uy, uz, fx, fy, fz, rest, dz) + tof;
         const CellVals v = load_cell<LAYOUT>(g, rs, off, dz, 0);
-        return fmaf(g.w_h2, rest, trilerp(fx, fy, fz, v.a, v.b, v.c, v.d));
+        return fmaf(g.w_h2, rest, interp<LAYOUT>(fx, fy, fz, v));
     } else if constexpr (LAYOUT == DOCK_LAYOUT_XY4) {
         // records wrap in x and y; the z neighbour is the record of plane jz
         const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
@@ -222,8 +239,8 @@ __device__ __forceinline__ float lookup_lane(const GridC &g, rsrc_t rs, uint32_t
         const int jz = iz + 1 == g.nz ? 0 : iz + 1;
         const float4 r0 = ld4(rs, tof + g.geo.offset(ix, iy, iz), 0);
         const float4 r1 = ld4(rs, tof + g.geo.offset(ix, iy, jz), 0);
-        return trilerp(fx, fy, fz, make_float2(r0.x, r0.y), make_float2(r0.z, r0.w), make_float2(r1.x, r1.y),
-                       make_float2(r1.z, r1.w));
+        return trilerp_dx(fx, fy, fz, make_float2(r0.x, r0.y), make_float2(r0.z, r0.w), make_float2(r1.x, r1.y),
+                          make_float2(r1.z, r1.w));
     } else {
         const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
         const float fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
@@ -433,7 +450,40 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
         float e[APL];
 #pragma unroll
         for (int j = 0; j < APL; ++j) e[j] = 0.0f;
-        int nsurv = 0;
+        int nsurv = 0, nbuilt = 0;
+
+        // fixed atoms: cylinder coordinates about the axis (radius +inf for the others, so that
+        // no pair with them passes the closest-approach test) and coordinates for the pair terms
+        float zj[2], rj[2];
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+            const int jj = lane + kWave * h2;
+            zj[h2] = 0.0f;
+            rj[h2] = INFINITY;
+            if (jj < n && !mask_has(mask, jj)) {
+                const float vx = cx[h2] - xax, vy = cy[h2] - xay, vz = cz[h2] - xaz;
+                zj[h2] = fmaf(ux, vx, fmaf(uy, vy, uz * vz));
+                const float ox = fmaf(-zj[h2], ux, vx), oy = fmaf(-zj[h2], uy, vy), oz = fmaf(-zj[h2], uz, vz);
+                rj[h2] = __builtin_amdgcn_sqrtf(fmaf(ox, ox, fmaf(oy, oy, oz * oz)));
+            }
+            if (jj < n) W.pos[jj] = make_float4(cx[h2], cy[h2], cz[h2], 0.0f);
+        }
+
+        // distance coefficients of the survivors [nbuilt, nsurv), whose moving slots refer to
+        // the coefficients currently in W.coef: d^2(t) = A + C cos t + D sin t
+        auto build = [&]() {
+            for (int i = nbuilt + lane; i < nsurv; i += kWave) {
+                const uint32_t id = W.sidx[i];
+                const Coef c = W.coef[id & 0xffu];
+                const float4 xj = W.pos[id >> 8];
+                const float wx = c.px - xj.x, wy = c.py - xj.y, wz = c.pz - xj.z;
+                const float A = fmaf(wx, wx, fmaf(wy, wy, fmaf(wz, wz, c.rho * c.rho)));
+                const float C = 2.0f * fmaf(wx, c.ax, fmaf(wy, c.ay, wz * c.az));
+                const float D = 2.0f * fmaf(wx, c.bx, fmaf(wy, c.by, wz * c.bz));
+                W.surv[i] = make_float4(A, C, D, 0.0f);
+            }
+            nbuilt = nsurv;
+        };
 
         // A kept pair clashes only on part of its circle: the penalty of an angle group is
         // evaluated only when some lane of the wavefront is inside the cut-off there.
@@ -527,37 +577,30 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
             }
             // (moving, fixed) clash pairs that can come within the cut-off somewhere on the circle
             for (int q = 0; q < cnt; ++q) {
-                const Coef c = W.coef[q];
+                const float rho = W.coef[q].rho, zq = W.coef[q].zz;
                 const uint4 ex = L.excl[W.atom[q]];
 #pragma unroll
                 for (int h2 = 0; h2 < 2; ++h2) {
                     if (kWave * h2 >= n) break;
                     const int jj = lane + kWave * h2;
-                    bool keep = false;
-                    float A = 0.0f, C = 0.0f, D = 0.0f;
-                    if (jj < n && !mask_has(mask, jj) && !mask_has(ex, jj)) {
-                        const float vx = cx[h2] - xax, vy = cy[h2] - xay, vz = cz[h2] - xaz;
-                        const float zj = fmaf(ux, vx, fmaf(uy, vy, uz * vz));
-                        const float ox = fmaf(-zj, ux, vx), oy = fmaf(-zj, uy, vy), oz = fmaf(-zj, uz, vz);
-                        const float rj = __builtin_amdgcn_sqrtf(fmaf(ox, ox, fmaf(oy, oy, oz * oz)));
-                        const float dr = c.rho - rj, dz = c.zz - zj;
-                        keep = fmaf(dr, dr, dz * dz) < s.cut2_keep;
-                        const float wx = c.px - cx[h2], wy = c.py - cy[h2], wz = c.pz - cz[h2];
-                        A = fmaf(wx, wx, fmaf(wy, wy, fmaf(wz, wz, c.rho * c.rho)));
-                        C = 2.0f * fmaf(wx, c.ax, fmaf(wy, c.ay, wz * c.az));
-                        D = 2.0f * fmaf(wx, c.bx, fmaf(wy, c.by, wz * c.bz));
-                    }
+                    const float dr = rho - rj[h2], dz = zq - zj[h2];
+                    const bool keep = fmaf(dr, dr, dz * dz) < s.cut2_keep && !mask_has(ex, jj);
                     const uint64_t kb = __ballot(keep);
-                    if (keep) W.surv[nsurv + lanes_below(kb)] = make_float4(A, C, D, 0.0f);
+                    if (keep) W.sidx[nsurv + lanes_below(kb)] = (uint16_t)(q | (jj << 8));
                     nsurv += __popcll(kb);
                     if (nsurv >= kWave) {
                         wave_sync();
+                        build();
+                        wave_sync();
                         flush(nsurv);
-                        nsurv = 0;
+                        nsurv = nbuilt = 0;
                         wave_sync();
                     }
                 }
             }
+            // the next half overwrites W.coef: form the pending survivors' coefficients now
+            wave_sync();
+            build();
             wave_sync();
         }
         if (nsurv) {
