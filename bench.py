@@ -72,7 +72,6 @@ def cpu_baseline(W, ligs, budget_s):
 def prefilter_bench(args):
     """Surrogate-filtered screening against plain docking on the same GPU."""
     import numpy as np
-    import torch
 
     from paper_2304_09953_amd import inputs as I
     from paper_2304_09953_amd import pipeline as P
@@ -85,14 +84,26 @@ def prefilter_bench(args):
     train = I.make_ligands(args.pf_train, W.dist, W.n_types, stream="train")
     sur = PF.train_surrogate(dp, ds, train, n_holdout=args.pf_train // 5, epochs=args.pf_epochs, log=log)
     log(f"surrogate: {sur.metrics}")
-    res = PF.filtered_screen(sur, dp, ds, W.dist, W.n_types, args.pf_lib, args.pf_chunk, args.pf_frac,
+    if args.pf_frac > 0:
+        frac, how = args.pf_frac, "given"
+    else:  # smallest fraction reaching the target recall (plus a margin) on the held-out docked ligands
+        frac = PF.calibrate_fraction(sur.holdout_pred, sur.holdout_true, args.pf_target + args.pf_margin)
+        how = (f"smallest with held-out recall >= {args.pf_target + args.pf_margin:.2f} "
+               f"({len(sur.holdout_true)} held-out docked ligands)")
+    log(f"docking the top {frac:.1%} by prediction ({how})")
+    res = PF.filtered_screen(sur, dp, ds, W.dist, W.n_types, args.pf_lib, args.pf_chunk, frac,
                              sample_every=args.pf_sample_every, log=log)
-    recall = PF.recall_top(res["sample_ids"], res["sample_scores"], res["selected_ids"], 0.01)
-    # ablations at the same budget: random, heaviest ligands first, linear model on the same features
-    n_s = len(res["sample_ids"])
+    sid, ssc = res["sample_ids"], res["sample_scores"].astype(np.float64)
+    recall = PF.recall_top(sid, ssc, res["selected_ids"], 0.01)
+    fracs = [0.01, 0.02, 0.03, 0.05, 0.075, 0.1, 0.15, 0.2, 0.3]
+    curve = PF.recall_curve(PF.ranks(res["predictions"])[sid], ssc, fracs + [frac], args.pf_lib)
+    # the method without the network, at the same budgets: largest ligands first (ties by id), random
+    size_rank = PF.ranks(-res["n_atoms"].astype(np.float64))[sid]
+    curve_size = PF.recall_curve(size_rank, ssc, fracs + [frac], args.pf_lib)
     rng = np.random.default_rng(0)
-    rand_sel = rng.choice(args.pf_lib, res["n_selected"], replace=False)
-    n_sample = len(res["sample_ids"])
+    rand_rank = rng.permutation(args.pf_lib)[sid]
+    curve_rand = PF.recall_curve(rand_rank, ssc, fracs + [frac], args.pf_lib)
+    n_sample = len(sid)
     plain_rate = n_sample / res["seconds_dock_sample"]
     filtered_seconds = res["seconds_predict"] + res["seconds_dock_selected"]
     out = {
@@ -100,17 +111,23 @@ def prefilter_bench(args):
         "value": recall, "unit": "recall", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
         "dtype": "bf16 MLP (FP32 accumulation), f32 docking",
         "config": {"workload": f"{W.name}; surrogate trained on {args.pf_train} docked ligands; library of "
-                               f"{args.pf_lib} streamed in chunks of {args.pf_chunk}; top {args.pf_frac:.0%} docked; "
+                               f"{args.pf_lib} streamed in chunks of {args.pf_chunk}; top {frac:.1%} docked ({how}); "
                                f"recall sample = ids divisible by {args.pf_sample_every} ({n_sample} ligands)"},
+        "selected_fraction": frac,
+        "target_recall": args.pf_target,
         "surrogate": sur.metrics,
         "filtered_ligands_per_s": args.pf_lib / filtered_seconds,
         "plain_ligands_per_s": plain_rate,
         "plain_seconds_extrapolated": args.pf_lib / plain_rate,
         "filtered_seconds": filtered_seconds,
+        "seconds_predict": res["seconds_predict"],
+        "seconds_dock_selected": res["seconds_dock_selected"],
         "speedup": (args.pf_lib / filtered_seconds) / plain_rate,
-        "recall_random_filter": PF.recall_top(res["sample_ids"], res["sample_scores"], rand_sel, 0.01),
+        "recall_curve": {f"{k:.3f}": v for k, v in curve.items()},
+        "recall_curve_largest_first": {f"{k:.3f}": v for k, v in curve_size.items()},
+        "recall_curve_random": {f"{k:.3f}": v for k, v in curve_rand.items()},
         "host_generation_seconds": res["seconds_generate_on_host"],
-        "n_sample": n_s,
+        "n_sample": n_sample,
     }
     print(json.dumps(out), flush=True)
 
@@ -133,8 +150,11 @@ def main():
     ap.add_argument("--pf-train", type=int, default=200_000)
     ap.add_argument("--pf-lib", type=int, default=10_000_000)
     ap.add_argument("--pf-chunk", type=int, default=1_000_000)
-    ap.add_argument("--pf-sample-every", type=int, default=20)
-    ap.add_argument("--pf-frac", type=float, default=0.03)
+    ap.add_argument("--pf-sample-every", type=int, default=50)
+    ap.add_argument("--pf-frac", type=float, default=0.0,
+                    help="fraction docked after the filter; 0 = calibrated on the held-out docked ligands")
+    ap.add_argument("--pf-target", type=float, default=0.95, help="recall of the true top 1%% to reach")
+    ap.add_argument("--pf-margin", type=float, default=0.02, help="added to the target when calibrating")
     ap.add_argument("--pf-epochs", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -48,6 +48,8 @@ class Surrogate:
     y_mean: float
     y_std: float
     metrics: dict = field(default_factory=dict)
+    holdout_pred: np.ndarray | None = None  # predicted and docked best scores of the held-out ligands
+    holdout_true: np.ndarray | None = None
 
     def predict_library(self, lib_dev) -> np.ndarray:
         """Predicted best score of every ligand of a DeviceLibrary, as the network's z-score (a
@@ -92,6 +94,7 @@ def train_surrogate(pocket_dev, search_dev, train_ligs, labels: np.ndarray | Non
         yh = y[n_tr:]
         metrics["holdout_r2"] = float(1 - np.sum((pred - yh) ** 2) / np.sum((yh - yh.mean()) ** 2))
         metrics["holdout_spearman"] = float(spearmanr(pred, yh).statistic)
+        s.holdout_pred, s.holdout_true = pred, yh
     s.metrics = metrics
     return s
 
@@ -102,6 +105,7 @@ def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, 
     prediction.  With sample_every > 0 the ligands whose id is a multiple of it are also docked in
     full during the same pass (the recall sample; timed separately).  Returns ids, scores, timings."""
     preds = np.empty(n_lib, dtype=np.float32)
+    n_atoms = np.empty(n_lib, dtype=np.int16)
     t_gen = t_pred = t_sample = 0.0
     s_ids, s_scores = [], []
     for s in range(0, n_lib, chunk):
@@ -112,6 +116,7 @@ def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, 
         p0 = time.perf_counter()
         preds[s:s + ligs.n_lig] = sur.predict_library(P.DeviceLibrary(ligs))
         t_pred += time.perf_counter() - p0
+        n_atoms[s:s + ligs.n_lig] = ligs.n_atoms
         if sample_every:
             loc = np.flatnonzero(ligs.ids % sample_every == 0)
             sub = ligs.subset(loc)
@@ -143,12 +148,43 @@ def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, 
         t_dock += time.perf_counter() - d0
         if log:
             log(f"docked selection up to id {s + chunk}")
-    out = {"selected_ids": sel, "selected_scores": scores, "predictions": preds, "seconds_predict": t_pred,
+    out = {"selected_ids": sel, "selected_scores": scores, "predictions": preds, "n_atoms": n_atoms,
+           "seconds_predict": t_pred,
            "seconds_dock_selected": t_dock, "seconds_generate_on_host": t_gen, "n_selected": len(sel)}
     if sample_every:
         out.update(sample_ids=np.concatenate(s_ids), sample_scores=np.concatenate(s_scores),
                    seconds_dock_sample=t_sample)
     return out
+
+
+def ranks(keys: np.ndarray, ids: np.ndarray | None = None) -> np.ndarray:
+    """Rank of every entry when sorted by key, ties to the lower id (the selection order of dock_topk)."""
+    ids = np.arange(len(keys)) if ids is None else ids
+    order = np.lexsort((ids, keys))
+    r = np.empty(len(keys), dtype=np.int64)
+    r[order] = np.arange(len(keys))
+    return r
+
+
+def recall_curve(key_rank: np.ndarray, true_scores: np.ndarray, fracs, n_total: int, top: float = 0.01) -> dict:
+    """For a set of docked ligands with known scores and their rank in the full library's selection
+    order: the share of the set's true top `top` that a selection of the first f * n_total ligands
+    keeps, for each f."""
+    k = max(1, int(round(top * len(true_scores))))
+    best = np.lexsort((np.arange(len(true_scores)), true_scores))[:k]
+    return {float(f): float(np.mean(key_rank[best] < int(round(f * n_total)))) for f in fracs}
+
+
+def calibrate_fraction(pred: np.ndarray, true: np.ndarray, target: float, top: float = 0.01,
+                       grid=np.round(np.arange(0.005, 1.0001, 0.005), 3)) -> float:
+    """Smallest selection fraction whose recall of the true top `top` on a docked held-out set reaches
+    `target` (1.0 if none does)."""
+    r = ranks(pred)
+    curve = recall_curve(r, true, grid, len(pred), top)
+    for f in grid:
+        if curve[float(f)] >= target:
+            return float(f)
+    return 1.0
 
 
 def recall_top(sample_ids: np.ndarray, sample_scores: np.ndarray, selected_ids: np.ndarray, frac: float = 0.01):

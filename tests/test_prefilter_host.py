@@ -1,0 +1,38 @@
+"""Host-side selection logic of the pre-filter workflow (no GPU): ranks, recall curves and the
+calibration of the docked fraction."""
+import numpy as np
+
+from paper_2304_09953_amd import prefilter as PF
+
+
+def test_ranks_break_ties_by_id():
+    keys = np.array([3.0, 1.0, 3.0, 1.0, np.inf])
+    assert PF.ranks(keys).tolist() == [2, 0, 3, 1, 4]
+    assert PF.ranks(keys, np.array([9, 8, 7, 6, 5])).tolist() == [3, 1, 2, 0, 4]
+
+
+def test_recall_curve_counts_the_kept_share_of_the_true_top():
+    rng = np.random.default_rng(0)
+    true = rng.normal(size=1000)
+    perfect = PF.ranks(true)                      # selection order = true order
+    c = PF.recall_curve(perfect, true, [0.005, 0.01, 0.02], 1000)
+    assert c == {0.005: 0.5, 0.01: 1.0, 0.02: 1.0}
+    worst = PF.ranks(-true)
+    assert PF.recall_curve(worst, true, [0.5, 0.99, 1.0], 1000) == {0.5: 0.0, 0.99: 0.0, 1.0: 1.0}
+    # a sample of a larger library: ranks are library-wide
+    c = PF.recall_curve(np.arange(0, 2000, 2), true, [0.01], 2000)
+    top = np.argsort(true, kind="stable")[:10]
+    assert c[0.01] == np.mean(2 * top < 20)
+
+
+def test_calibrate_fraction():
+    rng = np.random.default_rng(1)
+    true = rng.normal(size=4000)
+    assert PF.calibrate_fraction(true, true, 0.95) == 0.01
+    noisy = true + rng.normal(scale=0.3, size=4000)
+    f = PF.calibrate_fraction(noisy, true, 0.95)
+    assert 0.01 < f < 1.0
+    r = PF.ranks(noisy)
+    assert PF.recall_curve(r, true, [f], 4000)[f] >= 0.95
+    assert list(PF.recall_curve(r, true, [f - 0.005], 4000).values())[0] < 0.95
+    assert PF.calibrate_fraction(-true, true, 0.95) == 1.0
