@@ -82,7 +82,8 @@ def prefilter_bench(args):
     ds = P.DeviceSearch(W.search)
     log(f"labels: docking {args.pf_train} training ligands")
     train = I.make_ligands(args.pf_train, W.dist, W.n_types, stream="train")
-    sur = PF.train_surrogate(dp, ds, train, n_holdout=args.pf_train // 5, epochs=args.pf_epochs, log=log)
+    sur = PF.train_surrogate(dp, ds, train, n_holdout=args.pf_train // 5, members=args.pf_members,
+                             max_epochs=args.pf_epochs, log=log)
     log(f"surrogate: {sur.metrics}")
     if args.pf_frac > 0:
         frac, how = args.pf_frac, "given"
@@ -155,7 +156,8 @@ def main():
                     help="fraction docked after the filter; 0 = calibrated on the held-out docked ligands")
     ap.add_argument("--pf-target", type=float, default=0.95, help="recall of the true top 1%% to reach")
     ap.add_argument("--pf-margin", type=float, default=0.02, help="added to the target when calibrating")
-    ap.add_argument("--pf-epochs", type=int, default=30)
+    ap.add_argument("--pf-epochs", type=int, default=20, help="most epochs per member (early stopping)")
+    ap.add_argument("--pf-members", type=int, default=4, help="networks in the ensemble")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the screen has no multi-GPU path (a library would be sharded "

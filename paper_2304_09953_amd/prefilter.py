@@ -2,14 +2,16 @@
 by data the workflow itself generates, §2).
 
 1. Labels: best docking scores of a training library from the GPU screen.
-2. Features -> statistics -> normalised BF16 inputs; training with Adam on the matrix cores.
-3. Held-out R^2 and Spearman correlation.
+2. Features -> statistics -> normalised BF16 inputs; an ensemble of networks trained with Adam on
+   the matrix cores, each stopped early on a validation split.
+3. Held-out R^2 and Spearman correlation; the docked fraction is calibrated on the held-out ligands.
 4. Filtered screening of a library streamed in chunks: features and predictions for every ligand,
    global top fraction by prediction, docking of the selected ligands only.
 5. Recall of the true top 1 % of a fully docked sample.
 
-Every computational step runs in the library's kernels; this module orders the calls and moves
-ligand chunks between host and device.
+Every computational step of a network runs in the library's kernels; this module orders the calls,
+moves ligand chunks between host and device, and does the host-side bookkeeping (the members' mean,
+validation error, ranks and recall).
 """
 from __future__ import annotations
 
@@ -42,7 +44,7 @@ def library_chunk(dist, n_types, first_id: int, n: int, stream: str = "lib"):
 
 @dataclass
 class Surrogate:
-    model: SG.Model
+    models: list
     mean: torch.Tensor
     istd: torch.Tensor
     y_mean: float
@@ -51,47 +53,78 @@ class Surrogate:
     holdout_pred: np.ndarray | None = None  # predicted and docked best scores of the held-out ligands
     holdout_true: np.ndarray | None = None
 
+    def predict_z(self, xb: torch.Tensor) -> np.ndarray:
+        """Mean of the members' outputs (z-scores of the best docking score) for BF16 features."""
+        return np.mean([m.predict(xb).cpu().numpy().astype(np.float64) for m in self.models], axis=0)
+
     def predict_library(self, lib_dev) -> np.ndarray:
-        """Predicted best score of every ligand of a DeviceLibrary, as the network's z-score (a
+        """Predicted best score of every ligand of a DeviceLibrary, as the ensemble's z-score (a
         monotone map of the score, so rankings are those of the scores); +inf where the ligand's
         status is not OK."""
         _, xb = SG.features(lib_dev, self.mean, self.istd, f32=False, bf16=True)
-        z = self.model.predict(xb).cpu().numpy()
+        z = self.predict_z(xb).astype(np.float32)
         return np.where(lib_dev.status.cpu().numpy() == 0, z, np.float32(np.inf))
 
 
 def train_surrogate(pocket_dev, search_dev, train_ligs, labels: np.ndarray | None = None, n_holdout: int = 40_000,
-                    epochs: int = 30, batch: int = 1024, lr: float = 1e-3, seed: int = 0, log=None) -> Surrogate:
-    """Labels the training library by docking (unless given), trains on all but the last
-    n_holdout ligands (feature statistics from the training part only) and reports held-out R^2
-    and Spearman.  The generated libraries hold valid ligands only."""
+                    n_val: int | None = None, members: int = 4, max_epochs: int = 20, batch: int = 1024,
+                    lr: float = 1e-3, seed: int = 0, log=None) -> Surrogate:
+    """Labels the training library by docking (unless given) and splits it, in order, into training,
+    validation (n_val, default n_holdout / 2) and held-out (n_holdout) ligands.  Feature statistics
+    come from the training part.  Each of `members` networks (its own seed for the initial weights
+    and the sample order) trains for up to max_epochs and keeps the weights of the epoch with the
+    lowest validation error (early stopping); the prediction is the members' mean.  Reports
+    held-out R^2 and Spearman.  The generated libraries hold valid ligands only."""
+    n_val = n_holdout // 2 if n_val is None else n_val
     t0 = time.perf_counter()
     if labels is None:
         labels = dock_scores(pocket_dev, search_dev, train_ligs, log=log)
     t_label = time.perf_counter() - t0
     lib = P.DeviceLibrary(train_ligs)
     assert np.all(lib.status.cpu().numpy() == 0) and np.all(np.isfinite(labels))
-    n_tr = train_ligs.n_lig - n_holdout
+    n_tr = train_ligs.n_lig - n_holdout - n_val
+    assert n_tr > 0
     F, _ = SG.features(lib, bf16=False)
     mean, istd = SG.feature_stats(F[:n_tr])
     _, Xb = SG.features(lib, mean, istd, f32=False, bf16=True)
+    del F
     y = labels.astype(np.float64)
     y_mean, y_std = float(y[:n_tr].mean()), float(y[:n_tr].std())
-    z = torch.as_tensor(((y - y_mean) / y_std).astype(np.float32), device=F.device)
-    model = SG.Model(I.mlp_init(seed=seed))
+    z = torch.as_tensor(((y - y_mean) / y_std).astype(np.float32), device=Xb.device)
     Xtr, ztr = Xb[:n_tr], z[:n_tr]
+    Xva, zva = Xb[n_tr:n_tr + n_val], (y[n_tr:n_tr + n_val] - y_mean) / y_std
     t1 = time.perf_counter()
-    hist = SG.train(model, Xtr, ztr, epochs=epochs, batch=batch, lr=lr, seed=seed, log=log)
+    models, best_epochs, hist = [], [], []
+    for mbr in range(members):
+        model = SG.Model(I.mlp_init(seed=seed + mbr))
+        best, best_ep, best_w = np.inf, -1, model.master.clone()
+        for ep in range(max_epochs):
+            h = SG.train(model, Xtr, ztr, epochs=1, batch=batch, lr=lr, seed=(seed + mbr) * 100003 + ep)
+            if mbr == 0:
+                hist += h
+            if n_val:
+                err = float(np.mean((model.predict(Xva).cpu().numpy().astype(np.float64) - zva) ** 2))
+                if err < best:
+                    best, best_ep = err, ep
+                    best_w.copy_(model.master)
+            if log:
+                log(f"member {mbr}, epoch {ep + 1}/{max_epochs}: train loss {h[0]:.4f}" +
+                    (f", validation {err:.4f}" if n_val else ""))
+        if n_val:
+            model.master.copy_(best_w)
+            model.cast()
+        models.append(model)
+        best_epochs.append(best_ep + 1 if n_val else max_epochs)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    s = Surrogate(model, mean, istd, y_mean, y_std)
-    metrics = {"n_train": int(n_tr), "n_holdout": int(n_holdout), "epochs": epochs, "batch": batch,
-               "label_seconds": t_label, "train_seconds": t_train, "loss_first_epoch": hist[0],
-               "loss_last_epoch": hist[-1]}
+    s = Surrogate(models, mean, istd, y_mean, y_std)
+    metrics = {"n_train": int(n_tr), "n_validation": int(n_val), "n_holdout": int(n_holdout), "members": members,
+               "max_epochs": max_epochs, "best_epochs": best_epochs, "batch": batch, "label_seconds": t_label,
+               "train_seconds": t_train, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
     if n_holdout:
         from scipy.stats import spearmanr
-        pred = model.predict(Xb[n_tr:]).cpu().numpy().astype(np.float64) * y_std + y_mean
-        yh = y[n_tr:]
+        pred = s.predict_z(Xb[n_tr + n_val:]) * y_std + y_mean
+        yh = y[n_tr + n_val:]
         metrics["holdout_r2"] = float(1 - np.sum((pred - yh) ** 2) / np.sum((yh - yh.mean()) ** 2))
         metrics["holdout_spearman"] = float(spearmanr(pred, yh).statistic)
         s.holdout_pred, s.holdout_true = pred, yh

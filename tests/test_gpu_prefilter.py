@@ -1,0 +1,62 @@
+"""The learned pre-filter end to end on the GPU: what the trained network gains over selecting
+without it, and the filtered workflow's selection and docking against plain docking."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2304_09953_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def trained():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_09953_amd import pipeline as P
+    from paper_2304_09953_amd import prefilter as PF
+    W = I.workload("pocket96-lib100k")
+    dp, ds = P.DevicePocket(W.pockets[0]), P.DeviceSearch(W.search)
+    ligs = I.make_ligands(6000, W.dist, W.n_types, stream="test")
+    say("dock 6000 training ligands (full search), train a 2-member ensemble")
+    sur = PF.train_surrogate(dp, ds, ligs, n_holdout=1500, n_val=500, members=2, max_epochs=10, batch=256)
+    say(f"surrogate metrics {sur.metrics}")
+    return P, PF, W, dp, ds, ligs, sur
+
+
+def test_network_beats_selection_without_it(trained):
+    P, PF, W, dp, ds, ligs, sur = trained
+    pred, true = sur.holdout_pred, sur.holdout_true
+    ho = np.arange(ligs.n_lig - 1500, ligs.n_lig)
+    fr = [0.1, 0.25]
+    net = PF.recall_curve(PF.ranks(pred), true, fr, len(true), top=0.05)
+    big = PF.recall_curve(PF.ranks(-ligs.n_atoms[ho].astype(np.float64)), true, fr, len(true), top=0.05)
+    small = PF.recall_curve(PF.ranks(ligs.n_atoms[ho].astype(np.float64)), true, fr, len(true), top=0.05)
+    say(f"recall of the true top 5 %: network {net}, largest first {big}, smallest first {small}, random = f")
+    assert sur.metrics["holdout_spearman"] > 0.8
+    for f in fr:
+        assert net[f] >= f + 0.4                       # random selection keeps a share f
+        assert net[f] > max(big[f], small[f]) + 0.1    # and the size heuristics less than the network
+
+
+def test_filtered_screen_selects_by_prediction_and_docks_like_plain(trained):
+    P, PF, W, dp, ds, ligs, sur = trained
+    say("filtered screen of a 3000-ligand library, top 20 %, every 3rd ligand also docked in full")
+    res = PF.filtered_screen(sur, dp, ds, W.dist, W.n_types, 3000, 1000, 0.2, stream="sample", sample_every=3)
+    preds = res["predictions"]
+    order = np.lexsort((np.arange(3000), preds))
+    assert np.array_equal(np.sort(order[:600]), res["selected_ids"])
+    lib = I.make_ligands(3000, W.dist, W.n_types, stream="sample")
+    plain = P.screen(dp, P.DeviceLibrary(lib), ds).best_score.cpu().numpy()
+    assert np.array_equal(res["selected_scores"], plain[res["selected_ids"]])
+    assert np.array_equal(res["sample_ids"], np.arange(0, 3000, 3))
+    assert np.array_equal(res["sample_scores"], plain[::3])
+    # recall from the selection equals the curve read from the prediction ranks
+    r = PF.recall_top(res["sample_ids"], res["sample_scores"], res["selected_ids"], 0.05)
+    c = PF.recall_curve(PF.ranks(preds)[res["sample_ids"]], res["sample_scores"].astype(np.float64), [0.2], 3000,
+                        top=0.05)
+    assert r == c[0.2]
