@@ -118,6 +118,9 @@ def prefilter_bench(args):
         "target_recall": args.pf_target,
         "surrogate": sur.metrics,
         "filtered_ligands_per_s": args.pf_lib / filtered_seconds,
+        # the same with the one-off cost of docking the training ligands and training the networks
+        "filtered_ligands_per_s_incl_training": args.pf_lib / (filtered_seconds + sur.metrics["label_seconds"]
+                                                               + sur.metrics["train_seconds"]),
         "plain_ligands_per_s": plain_rate,
         "plain_seconds_extrapolated": args.pf_lib / plain_rate,
         "filtered_seconds": filtered_seconds,
