@@ -136,6 +136,50 @@ def prefilter_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def calibrate_peaks(args):
+    """Measured peaks of this GPU: non-packed FP32 FMA rate and read bandwidth of a buffer resident
+    in the L2 caches (2 MiB, read by every block) and of one resident in the Infinity Cache only
+    (64 MiB, larger than all L2s together)."""
+    import torch
+
+    from paper_2304_09953_amd import dock
+    out = {}
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    blocks, iters = 8192, 2048
+    sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    dock.calib_fma_f32(blocks, 16, sink)
+    torch.cuda.synchronize()
+    best = 0.0
+    for _ in range(3):
+        e0, e1 = ev(), ev()
+        e0.record()
+        dock.calib_fma_f32(blocks, iters, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, blocks * 256 * iters * 32 / (e0.elapsed_time(e1) * 1e-3))
+    out["fma_f32_tflops"] = best / 1e12
+    log(f"FMA: {best / 1e12:.1f} TFLOP/s")
+    for name, mib, blk, reps in (("l2", 2, 2048, 64), ("mall", 64, 512, 2)):
+        if args.calibrate_peaks != "all" and args.calibrate_peaks != name:
+            continue
+        buf = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+        sink = torch.empty(blk * 256, dtype=torch.float32, device="cuda")
+        dock.calib_cache_read(buf, 1, blk, sink)
+        torch.cuda.synchronize()
+        best = 0.0
+        for _ in range(3):
+            e0, e1 = ev(), ev()
+            e0.record()
+            dock.calib_cache_read(buf, reps, blk, sink)
+            e1.record()
+            torch.cuda.synchronize()
+            best = max(best, blk * reps * (mib << 20) / (e0.elapsed_time(e1) * 1e-3))
+        out[f"{name}_read_tbps"] = best / 1e12
+        out[f"{name}_read_bytes_per_launch"] = blk * reps * (mib << 20)
+        log(f"{name} ({mib} MiB buffer): {best / 1e12:.2f} TB/s")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +188,8 @@ def main():
     ap.add_argument("--n-lig", type=int, default=None, help="dock only the first N ligands (a subset workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-peaks", choices=("all", "l2", "mall", "fma"), default=None,
+                    help="measure the FMA rate and cache-resident read bandwidth of this GPU, then exit")
     ap.add_argument("--layout", choices=("xy4", "linear"), default="xy4",
                     help="grid layout: 16-byte records of the four xy neighbours, or plain [t][z][y][x]")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -185,6 +231,8 @@ def main():
         print(json.dumps({"copy_bytes": 4 * n, "launches": 1}), flush=True)
         return
     dock.load()  # fails loudly if the HIP library is missing
+    if args.calibrate_peaks:
+        return calibrate_peaks(args)
     if args.prefilter:
         return prefilter_bench(args)
     W = I.workload("pocket96-lib100k")

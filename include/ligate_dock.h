@@ -62,9 +62,10 @@ extern "C" {
 #define DOCK_LAYOUT_XY4 1        /* per node a 16-byte record of its z plane: G(x, y),
                                     G(x+1, y) - G(x, y), G(x, y+1), G(x+1, y+1) - G(x, y+1)
                                     (differences rounded to FP32; indices beyond the last node wrap
-                                    to 0), stored in bricks of 2 x 2 x 2 records (128 bytes) with
-                                    dimensions rounded up to even; about 4x the memory, and a
-                                    trilinear lookup reads two records, mostly from one line */
+                                    to 0), stored as [t][z/2][y/2][x][z&1][y&1] with dimensions
+                                    rounded up to even, so that a 128-byte line holds 2 x 2 x 2
+                                    records; about 4x the memory, and a trilinear lookup reads two
+                                    records, mostly from one line */
 #define DOCK_BOUNDARY_CLAMP 0    /* clamp into the box + w_out * |x - clamp(x)|^2 */
 #define DOCK_BOUNDARY_PERIODIC 1 /* indices wrap modulo the grid size */
 

@@ -32,20 +32,21 @@ int check_launch(const char *what);
 // Grid storage
 // ---------------------------------------------------------------------------------------------
 
-// DOCK_LAYOUT_XY4 storage order: the 16-byte records are grouped in bricks of 2 x 2 x 2 records,
-// one 128-byte cache line each.  Brick (bx, by, bz) has index bx + nbx (by + nby bz); record
-// (x, y, z) sits at position (x & 1) + 2 (y & 1) + 4 (z & 1) inside its brick.  A trilinear lookup
-// reads the records (x0, y0, z0) and (x0, y0, z0 + 1), usually from the same line, and the lookups
-// of neighbouring points share lines in all three directions.
+// DOCK_LAYOUT_XY4 storage order: the 16-byte records are grouped in bricks of 1 x 2 x 2 records
+// (64 bytes), the records of a (y, z) pair of rows; brick (x, by, bz) has index
+// x + nxp (by + nby bz) with nxp = nx rounded up to even, and record (x, y, z) sits at position
+// (y & 1) + 2 (z & 1) inside its brick.  A 128-byte line thus holds the 2 x 2 x 2 records of
+// x = 2i, 2i + 1.  A trilinear lookup reads the records (x0, y0, z0) and (x0, y0, z0 + 1), usually
+// from the same line, and the lookups of neighbouring points share lines in all three directions.
 struct Xy4Geom {
-    uint32_t nbx, nby, nbz;  // bricks per axis, ceil(n / 2)
+    uint32_t nxp, nby, nbz;  // nx rounded up to even; ceil(ny / 2), ceil(nz / 2)
 
     __host__ __device__ static Xy4Geom of(int nx, int ny, int nz) {
-        return Xy4Geom{(uint32_t)(nx + 1) / 2, (uint32_t)(ny + 1) / 2, (uint32_t)(nz + 1) / 2};
+        return Xy4Geom{(uint32_t)(nx + 1) & ~1u, (uint32_t)(ny + 1) / 2, (uint32_t)(nz + 1) / 2};
     }
-    __host__ __device__ uint64_t type_bytes() const { return 128ull * nbx * nby * nbz; }
+    __host__ __device__ uint64_t type_bytes() const { return 64ull * nxp * nby * nbz; }
     __host__ __device__ uint32_t offset(uint32_t x, uint32_t y, uint32_t z) const {
-        return 128u * ((x >> 1) + nbx * ((y >> 1) + nby * (z >> 1))) + 16u * ((x & 1u) + 2u * (y & 1u) + 4u * (z & 1u));
+        return 64u * (x + nxp * ((y >> 1) + nby * (z >> 1))) + 16u * ((y & 1u) + 2u * (z & 1u));
     }
 };
 
@@ -151,6 +152,21 @@ __device__ __forceinline__ void wave_sync() {
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Minimum of two values that are never NaN: one v_min_f32, without the quieting of signalling
+// NaNs that fminf adds to each operand.
+__device__ __forceinline__ float min_nonan(float a, float b) {
+    float r;
+    asm volatile("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Wave minimum of values that are never NaN.
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min_nonan(v, __shfl_xor(v, off));
     return v;
 }
 

@@ -75,10 +75,10 @@ __global__ __launch_bounds__(kGridBlock) void k_xy4_diff(float4 *__restrict__ re
     if (i >= n) return;
     const Xy4Geom geo = Xy4Geom::of(nx, ny, nz);
     const int64_t r_type = (int64_t)(geo.type_bytes() / 16);
-    const uint32_t in_type = (uint32_t)(i % r_type), brick = in_type >> 3, pos = in_type & 7u;
-    const uint32_t x = 2u * (brick % geo.nbx) + (pos & 1u);
-    const uint32_t y = 2u * ((brick / geo.nbx) % geo.nby) + ((pos >> 1) & 1u);
-    const uint32_t z = 2u * (brick / (geo.nbx * geo.nby)) + (pos >> 2);
+    const uint32_t in_type = (uint32_t)(i % r_type), brick = in_type >> 2, pos = in_type & 3u;
+    const uint32_t x = brick % geo.nxp;
+    const uint32_t y = 2u * ((brick / geo.nxp) % geo.nby) + (pos & 1u);
+    const uint32_t z = 2u * (brick / (geo.nxp * geo.nby)) + (pos >> 1);
     float4 r = rec[i];
     r.y = r.y - r.x;
     r.w = r.w - r.z;

@@ -40,11 +40,11 @@ struct GridC {
     // below 2^26 and multiples of 4, so exact in FP32)
     uint32_t row, plane;
     float frow, fplane;
-    // xy4 layout: the record offset is 16 x + 32 y + 64 z + kx (x >> 1) + ky (y >> 1) + kz (z >> 1)
-    // (exact in FP32: multiples of 16 below 2^28); the z + 1 record is 64 bytes further for even z
-    // and dz_odd further for odd z
+    // xy4 layout: the record offset is 64 x + 16 y + 32 z + ky (y >> 1) + kz (z >> 1) (exact in
+    // FP32: multiples of 16 below 2^28); the z + 1 record is 32 bytes further for even z and
+    // dz_odd further for odd z
     Xy4Geom geo;
-    float kx, ky, kz;
+    float ky, kz;
     uint32_t dz_odd;
     float mx, my, mz;          // n - 1: clamp bound
     float cx, cy, cz;          // n - 2: last cell
@@ -58,6 +58,7 @@ struct SearchC {
     int n_quat, n_trans, S, QT;
     float cut, cut2, cut2_keep, w;  // clash in grid units: cut-off / h, its square, (cut-off / h + margin)^2,
                                     // weight h^2
+    float sw, swc;                  // sqrt(w) and sqrt(w) cut
 };
 
 // Coordinates inside a start are in grid units (x - origin) / spacing throughout: the map is a
@@ -155,9 +156,9 @@ __device__ __forceinline__ uint32_t cell(const GridC &g, float ux, float uy, flo
     fy = qy - y0;
     fz = qz - z0;
     if constexpr (LAYOUT == DOCK_LAYOUT_XY4) {
-        const float bx = floorf(0.5f * x0), by = floorf(0.5f * y0), bz = floorf(0.5f * z0);
-        dz = z0 != 2.0f * bz ? g.dz_odd : 64u;
-        return (uint32_t)fmaf(x0, 16.0f, fmaf(bx, g.kx, fmaf(y0, 32.0f, fmaf(by, g.ky, fmaf(z0, 64.0f, bz * g.kz)))));
+        const float by = floorf(0.5f * y0), bz = floorf(0.5f * z0);
+        dz = z0 != 2.0f * bz ? g.dz_odd : 32u;
+        return (uint32_t)fmaf(x0, 64.0f, fmaf(y0, 16.0f, fmaf(by, g.ky, fmaf(z0, 32.0f, bz * g.kz))));
     } else {
         dz = g.plane;
         return (uint32_t)fmaf(z0, g.fplane, fmaf(y0, g.frow, 4.0f * x0));
@@ -447,9 +448,10 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
         float xax, xay, xaz, ux, uy, uz;
         axis(tr, cx, cy, cz, xax, xay, xaz, ux, uy, uz);
 
+        // angles past S start at +inf, so they never win the argmin
         float e[APL];
 #pragma unroll
-        for (int j = 0; j < APL; ++j) e[j] = 0.0f;
+        for (int j = 0; j < APL; ++j) e[j] = lane + kWave * j < s.S ? 0.0f : INFINITY;
         int nsurv = 0, nbuilt = 0;
 
         // fixed atoms: cylinder coordinates about the axis (radius +inf for the others, so that
@@ -487,15 +489,17 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
 
         // A kept pair clashes only on part of its circle: the penalty of an angle group is
         // evaluated only when some lane of the wavefront is inside the cut-off there.
+        // The penalty w (c - d)^2 is accumulated as t^2 with t = max(sqrt(w) c - sqrt(w) d, 0); d^2 that
+        // rounding made slightly negative (coincident atoms) is taken by magnitude.
         auto flush = [&](int cnt) {
             for (int q = 0; q < cnt; ++q) {
                 const float4 acd = W.surv[q];
 #pragma unroll
                 for (int j = 0; j < APL; ++j) {
-                    const float d2 = fmaxf(fmaf(acd.y, cs[j], fmaf(acd.z, sn[j], acd.x)), 0.0f);
+                    const float d2 = fmaf(acd.y, cs[j], fmaf(acd.z, sn[j], acd.x));
                     if (__ballot(d2 < s.cut2)) {
-                        const float t = fmaxf(s.cut - __builtin_amdgcn_sqrtf(d2), 0.0f);
-                        e[j] = fmaf(s.w * t, t, e[j]);
+                        const float t = fmaxf(fmaf(-s.sw, __builtin_amdgcn_sqrtf(fabsf(d2)), s.swc), 0.0f);
+                        e[j] = fmaf(t, t, e[j]);
                     }
                 }
             }
@@ -609,19 +613,18 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
             wave_sync();
         }
 
-        // argmin over the S steps, ties to the lowest step
-        uint64_t best = ~0ull;
+        // argmin over the S steps, ties to the lowest step: the wave minimum, then the first step
+        // (angle group j, then lane) that attains it
+        float emin = e[0];
 #pragma unroll
-        for (int j = 0; j < APL; ++j) {
-            const int st = lane + kWave * j;
-            if (st < s.S) {
-                const uint64_t key = ((uint64_t)float_to_ordered(e[j]) << 32) | (uint32_t)st;
-                best = key < best ? key : best;
-            }
+        for (int j = 1; j < APL; ++j) emin = min_nonan(emin, e[j]);
+        const float ebest = wave_min(emin);
+        int sbest = 0;
+#pragma unroll
+        for (int j = APL - 1; j >= 0; --j) {
+            const uint64_t hit = __ballot(e[j] == ebest);
+            if (hit) sbest = kWave * j + (int)__builtin_ctzll(hit);
         }
-        best = wave_min_u64(best);
-        const int sbest = (int)(uint32_t)best;
-        const float ebest = ordered_to_float((uint32_t)(best >> 32));
         const float e0 = __shfl(e[0], 0);
         E += ebest - e0;
         Emax = fmaxf(Emax, fabsf(E));
@@ -847,10 +850,9 @@ static GridC make_grid(const dock_grid_desc *d, const float *G) {
     g.frow = (float)g.row;
     g.fplane = (float)g.plane;
     g.geo = Xy4Geom::of(d->nx, d->ny, d->nz);
-    g.kx = 96.0f;
-    g.ky = 128.0f * (float)g.geo.nbx - 64.0f;
-    g.kz = 128.0f * (float)g.geo.nbx * (float)g.geo.nby - 128.0f;
-    g.dz_odd = 128u * g.geo.nbx * g.geo.nby - 64u;
+    g.ky = 64.0f * (float)g.geo.nxp - 32.0f;
+    g.kz = 64.0f * (float)g.geo.nxp * (float)g.geo.nby - 64.0f;
+    g.dz_odd = 64u * g.geo.nxp * g.geo.nby - 32u;
     g.inv_h = 1.0f / d->spacing;
     g.ox_h = d->origin[0] / d->spacing;
     g.oy_h = d->origin[1] / d->spacing;
@@ -891,6 +893,8 @@ static SearchC make_search(const dock_search *d, float spacing) {
     const float keep = s.cut + 1e-3f;  // pairs this close somewhere on the circle are kept
     s.cut2_keep = keep * keep;
     s.w = d->clash_w * spacing * spacing;
+    s.sw = sqrtf(s.w);
+    s.swc = s.sw * s.cut;
     return s;
 }
 

@@ -187,3 +187,36 @@ def score_poses(desc: GridDesc, grids, pack, n_lig: int, n_atoms: int, search: S
     _check(load().dock_score_poses(ctypes.byref(desc), _ptr(grids), _ptr(pack), n_lig, n_atoms, ctypes.byref(search),
                                    _ptr(lig), _ptr(start), _ptr(steps), lig.numel(), _ptr(out), _stream(stream)),
            "dock_score_poses")
+
+
+# ------------------------------------------------------------------------------------------------
+# Peak calibration (include/ligate_calib.h): measurement helpers, not part of the method
+# ------------------------------------------------------------------------------------------------
+
+CALIB_EXPORTS = ("calib_fma_f32", "calib_cache_read")
+_calib_bound = False
+
+
+def _calib_lib():
+    global _calib_bound
+    lib = load()
+    if not _calib_bound:
+        lib.calib_fma_f32.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+        lib.calib_cache_read.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_void_p]
+        for n in CALIB_EXPORTS:
+            getattr(lib, n).restype = ctypes.c_int
+        _calib_bound = True
+    return lib
+
+
+def calib_fma_f32(blocks: int, iters: int, out: torch.Tensor, stream=None):
+    """Enqueues blocks * 256 threads x iters x 16 non-packed FP32 FMA chains (32 FLOP per step)."""
+    _check(_calib_lib().calib_fma_f32(blocks, iters, _ptr(out), _stream(stream)), "calib_fma_f32")
+
+
+def calib_cache_read(buf: torch.Tensor, reps: int, blocks: int, out: torch.Tensor, stream=None):
+    """Enqueues blocks x reps full reads of buf (16-byte loads); blocks * reps * buf bytes in all."""
+    nbytes = buf.numel() * buf.element_size()
+    _check(_calib_lib().calib_cache_read(_ptr(buf), nbytes, reps, blocks, _ptr(out), _stream(stream)),
+           "calib_cache_read")

@@ -44,26 +44,27 @@ class DevicePocket:
 
     def _bricks(self):
         nx, ny, nz = self.pocket.dims
-        return (nx + 1) // 2, (ny + 1) // 2, (nz + 1) // 2
+        return (nx + 1) // 2 * 2, (ny + 1) // 2, (nz + 1) // 2
 
     def records(self):
-        """The xy4 records as [t][z][y][x][4] (a copy; storage is in 2 x 2 x 2 bricks of records)."""
+        """The xy4 records as [t][z][y][x][4] (a copy; storage is in bricks of the 1 x 2 x 2
+        records of a (y, z) pair of rows, [t][z/2][y/2][x][z&1][y&1][4])."""
         assert self.layout == dock.LAYOUT_XY4
         nx, ny, nz = self.pocket.dims
-        bx, by, bz = self._bricks()
+        xp, by, bz = self._bricks()
         T = self.pocket.n_types
-        r = self.grids.view(T, bz, by, bx, 2, 2, 2, 4).permute(0, 1, 4, 2, 5, 3, 6, 7)
-        return r.reshape(T, 2 * bz, 2 * by, 2 * bx, 4)[:, :nz, :ny, :nx].contiguous()
+        r = self.grids.view(T, bz, by, xp, 2, 2, 4).permute(0, 1, 4, 2, 5, 3, 6)
+        return r.reshape(T, 2 * bz, 2 * by, xp, 4)[:, :nz, :ny, :nx].contiguous()
 
     def write_records(self, rec: torch.Tensor):
         """Stores [t][z][y][x][4] records in brick order (the inverse of records())."""
         assert self.layout == dock.LAYOUT_XY4
         nx, ny, nz = self.pocket.dims
-        bx, by, bz = self._bricks()
+        xp, by, bz = self._bricks()
         T = self.pocket.n_types
-        full = torch.zeros((T, 2 * bz, 2 * by, 2 * bx, 4), dtype=torch.float32, device=self.grids.device)
+        full = torch.zeros((T, 2 * bz, 2 * by, xp, 4), dtype=torch.float32, device=self.grids.device)
         full[:, :nz, :ny, :nx] = rec
-        b = full.view(T, bz, 2, by, 2, bx, 2, 4).permute(0, 1, 3, 5, 2, 4, 6, 7)
+        b = full.view(T, bz, 2, by, 2, xp, 4).permute(0, 1, 3, 5, 2, 4, 6)
         self.grids.copy_(b.reshape(-1))
 
 

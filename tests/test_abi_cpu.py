@@ -9,7 +9,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("ligate_dock.h", "ligate_surrogate.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("ligate_dock.h", "ligate_surrogate.h", "ligate_calib.h")]
 
 
 def _lib():
@@ -40,10 +40,25 @@ def test_header_declares_the_abi():
 def test_library_exports_every_declared_symbol():
     dock, lib = _lib()
     from paper_2304_09953_amd import surrogate
-    for name in declared_functions("dock_") + declared_functions("surr_"):
+    for name in declared_functions("dock_") + declared_functions("surr_") + declared_functions("calib_"):
         assert hasattr(lib, name), name
     assert set(dock.EXPORTS) == set(declared_functions("dock_"))
     assert set(surrogate.SURR_EXPORTS) == set(declared_functions("surr_"))
+    assert set(dock.CALIB_EXPORTS) == set(declared_functions("calib_"))
+    # nothing else is declared: every function of every header carries one of the three prefixes
+    text = "".join(open(h).read() for h in HEADERS)
+    all_decl = set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\([^;]*\);", text, re.M | re.S))
+    assert all_decl == set(declared_functions("dock_") + declared_functions("surr_") + declared_functions("calib_"))
+
+
+def test_calib_argument_errors():
+    dock, _ = _lib()
+    lib = dock._calib_lib()
+    assert lib.calib_fma_f32(0, 10, ctypes.c_void_p(16), None) == -1
+    assert lib.calib_fma_f32(10, 10, None, None) == -1
+    assert lib.calib_cache_read(ctypes.c_void_p(16), 16384 + 4096, 1, 1, ctypes.c_void_p(16), None) == -1
+    assert lib.calib_cache_read(ctypes.c_void_p(8), 16384, 1, 1, ctypes.c_void_p(16), None) == -1
+    assert lib.calib_cache_read(ctypes.c_void_p(16), 16384, 0, 1, ctypes.c_void_p(16), None) == -1
 
 
 def test_surrogate_argument_errors():
