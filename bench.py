@@ -36,16 +36,84 @@ def screen_source_hash():
     return hashlib.sha256(open(SCREEN_SRC, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_counters():
-    """HBM bytes per screen launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; otherwise None."""
+def counters():
+    """The committed rocprofv3 counter summary of the screen, if it was taken on the current kernel
+    source; otherwise None."""
     try:
         c = json.load(open(COUNTERS))
     except (OSError, ValueError):
         return None
-    if c.get("screen_src_sha256_16") != screen_source_hash():
-        return None
-    return c.get("hbm_bytes_per_launch")
+    return c if c.get("screen_src_sha256_16") == screen_source_hash() else None
+
+
+def traffic_from_counters():
+    """HBM bytes per screen launch from the counter summary, or None."""
+    c = counters()
+    return None if c is None else c.get("hbm_bytes_per_launch")
+
+
+def _pmc(csv_dir, counter, kernel):
+    """Per-dispatch values of one counter for one kernel, from a rocprofv3 --pmc CSV directory."""
+    import csv
+    import glob
+    vals = {}
+    for f in glob.glob(os.path.join(csv_dir, "*counter_collection.csv")):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter and r["Kernel_Name"] == kernel:
+                vals[int(r["Dispatch_Id"])] = vals.get(int(r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
+    return [vals[k] for k in sorted(vals)]
+
+
+def summarize_counters(out_dir):
+    """Writes the counter summary (profiles/screen_counters.json) from the rocprofv3 --pmc runs
+    listed in its "commands" (their CSV directories under out_dir)."""
+    d = lambda name: os.path.join(out_dir, name)  # noqa: E731
+    one = lambda name, counter, kernel="k_screen": _pmc(d(name), counter, kernel)[0]  # noqa: E731
+    fetch, write = one("pmc_fetch", "FETCH_SIZE"), one("pmc_write", "WRITE_SIZE")
+    cf = one("pmc_copy_fetch", "FETCH_SIZE", "__amd_rocclr_copyBuffer")
+    cw = one("pmc_copy_write", "WRITE_SIZE", "__amd_rocclr_copyBuffer")
+    ff, fw = (1 << 20) / cf, (1 << 20) / cw  # KiB counted for a 1 GiB copy
+    req = one("pmc_req", "TCP_TCC_READ_REQ_sum")
+    # bytes per L1-to-L2 request: the cache-resident read kernel's known bytes over its requests
+    # (its three timed dispatches: 2048 blocks x 64 reads of 2 MiB)
+    creq = _pmc(d("pmc_req_calib"), "TCP_TCC_READ_REQ_sum", "k_calib_read")[-3:]
+    req_bytes = 3 * 2048 * 64 * (2 << 20) / sum(creq)
+    valu = one("pmc_valu", "SQ_INSTS_VALU")
+    gui = one("pmc_valu", "GRBM_GUI_ACTIVE")  # summed over the 8 XCDs
+    hit, miss = one("pmc_req", "TCC_HIT_sum"), one("pmc_req", "TCC_MISS_sum")
+    base = "cd /tmp && rocprofv3 --pmc {c} -T -f csv -d <repo>/gpurun_out/{d} -o {o} -- python3 -u <repo>/bench.py {a}"
+    run1 = "--no-cpu-baseline --steps 1 --warmup 0"
+    out = {
+        "kernel": "k_screen",
+        "workload": "pocket96-lib100k (100k ligands, 96^3 x 16 grid, 256 x 32 starts, 256 steps)",
+        "screen_src_sha256_16": screen_source_hash(),
+        "fetch_size_kib_per_launch": fetch, "write_size_kib_per_launch": write,
+        "copy_reference": {"bytes": 1 << 30, "fetch_size_kib": cf, "write_size_kib": cw, "fetch_factor": ff,
+                           "write_factor": fw},
+        "hbm_bytes_per_launch": fetch * 1024 * ff + write * 1024 * fw,
+        "l1_to_l2_requests_per_launch": req,
+        "l1_to_l2_request_bytes": req_bytes,
+        "l1_to_l2_bytes_per_launch": req * req_bytes,
+        "l2_hit_rate": hit / (hit + miss),
+        "valu_insts_per_launch": valu,
+        "gpu_cycles_per_launch": gui / 8,
+        "valu_busy": valu * 4 / (256 * 4) / (gui / 8),
+        "commands": [base.format(c="FETCH_SIZE", d="pmc_fetch", o="fetch", a=run1),
+                     base.format(c="WRITE_SIZE", d="pmc_write", o="write", a=run1),
+                     base.format(c="FETCH_SIZE", d="pmc_copy_fetch", o="copy", a="--calibrate-copy 1024"),
+                     base.format(c="WRITE_SIZE", d="pmc_copy_write", o="copy", a="--calibrate-copy 1024"),
+                     base.format(c="TCP_TCC_READ_REQ_sum TCC_HIT_sum TCC_MISS_sum", d="pmc_req", o="req", a=run1),
+                     base.format(c="TCP_TCC_READ_REQ_sum", d="pmc_req_calib", o="calib", a="--calibrate-peaks l2"),
+                     base.format(c="SQ_INSTS_VALU GRBM_GUI_ACTIVE", d="pmc_valu", o="valu", a=run1),
+                     f"python3 bench.py --summarize-counters <dir holding the CSV directories above>"],
+        "note": ("FETCH_SIZE/WRITE_SIZE count L2-to-fabric traffic in KiB per dispatch (Infinity Cache hits "
+                 "included), each scaled by what it reads for a plain 1 GiB device copy. L1-to-L2 requests are "
+                 "scaled by the bytes per request of the cache-resident read kernel. VALU busy = VALU "
+                 "instructions x 4 cycles (one wave64 instruction per SIMD every 4 cycles) over 1024 SIMDs x "
+                 "the kernel's cycles."),
+    }
+    json.dump(out, open(COUNTERS, "w"), indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def cpu_baseline(W, ligs, budget_s):
@@ -162,22 +230,32 @@ def calibrate_peaks(args):
     for name, mib, blk, reps in (("l2", 2, 2048, 64), ("mall", 64, 512, 2)):
         if args.calibrate_peaks != "all" and args.calibrate_peaks != name:
             continue
-        buf = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
-        sink = torch.empty(blk * 256, dtype=torch.float32, device="cuda")
-        dock.calib_cache_read(buf, 1, blk, sink)
-        torch.cuda.synchronize()
-        best = 0.0
-        for _ in range(3):
-            e0, e1 = ev(), ev()
-            e0.record()
-            dock.calib_cache_read(buf, reps, blk, sink)
-            e1.record()
-            torch.cuda.synchronize()
-            best = max(best, blk * reps * (mib << 20) / (e0.elapsed_time(e1) * 1e-3))
+        best = read_peak(mib, blk, reps)
         out[f"{name}_read_tbps"] = best / 1e12
         out[f"{name}_read_bytes_per_launch"] = blk * reps * (mib << 20)
         log(f"{name} ({mib} MiB buffer): {best / 1e12:.2f} TB/s")
     print(json.dumps(out), flush=True)
+
+
+def read_peak(mib=2, blk=2048, reps=64):
+    """Best of three cache-resident reads (one untimed first): each of blk blocks reads the mib MiB
+    buffer reps times; bytes/s."""
+    import torch
+
+    from paper_2304_09953_amd import dock
+    buf = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    sink = torch.empty(blk * 256, dtype=torch.float32, device="cuda")
+    dock.calib_cache_read(buf, 1, blk, sink)
+    torch.cuda.synchronize()
+    best = 0.0
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dock.calib_cache_read(buf, reps, blk, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, blk * reps * (mib << 20) / (e0.elapsed_time(e1) * 1e-3))
+    return best
 
 
 def main():
@@ -188,6 +266,8 @@ def main():
     ap.add_argument("--n-lig", type=int, default=None, help="dock only the first N ligands (a subset workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-counters", metavar="DIR", default=None,
+                    help="write the screen's counter summary from rocprofv3 --pmc CSV directories in DIR")
     ap.add_argument("--calibrate-peaks", choices=("all", "l2", "mall", "fma"), default=None,
                     help="measure the FMA rate and cache-resident read bandwidth of this GPU, then exit")
     ap.add_argument("--layout", choices=("xy4", "linear"), default="xy4",
@@ -208,6 +288,8 @@ def main():
     ap.add_argument("--pf-epochs", type=int, default=20, help="most epochs per member (early stopping)")
     ap.add_argument("--pf-members", type=int, default=4, help="networks in the ensemble")
     args = ap.parse_args()
+    if args.summarize_counters:
+        return summarize_counters(args.summarize_counters)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the screen has no multi-GPU path (a library would be sharded "
               "by ligand over independent processes). Use --gpus 1.", file=sys.stderr)
@@ -292,6 +374,22 @@ def main():
     achieved = flop / (screen_ms * 1e-3)
     best = scr.best_score.cpu().numpy()
     assert np.all(np.isfinite(best[ok]))
+    t_screen = screen_ms * 1e-3
+    c = counters() if n_lig == W.n_lig else None  # the counters are per launch of the full workload
+    l2_peak = read_peak()
+    log(f"L2-resident read peak: {l2_peak / 1e12:.2f} TB/s")
+    gather = {
+        "algorithmic_bytes_per_s": BYTES_PER_LOOKUP * lookups / t_screen,
+        "l1_to_l2_bytes_per_s": c["l1_to_l2_bytes_per_launch"] / t_screen if c else None,
+        "l2_read_peak_bytes_per_s": l2_peak,
+        "frac": c["l1_to_l2_bytes_per_launch"] / t_screen / l2_peak if c else None,
+        "l2_hit_rate": c["l2_hit_rate"] if c else None,
+        "hbm_side_bytes_per_s": c["hbm_bytes_per_launch"] / t_screen if c else None,
+        "hbm_side_frac": c["hbm_bytes_per_launch"] / t_screen / 8e12 if c else None,
+        "valu_busy": c["valu_busy"] if c else None,
+        "note": "L1-to-L2 request bytes (rocprofv3, per launch) over the measured L2-resident read peak; "
+                "HBM side = FETCH_SIZE + WRITE_SIZE (Infinity Cache hits included) over 8 TB/s",
+    }
 
     out = {
         "metric": METRIC,
@@ -317,6 +415,7 @@ def main():
                      "kernel": "k_screen (+ its planning and replay kernels, inside the same events)",
                      "algorithmic_flop_per_launch": flop, "lookups_per_launch": lookups,
                      "gather_bytes_per_s": BYTES_PER_LOOKUP * lookups / (screen_ms * 1e-3)},
+        "gather_roofline": gather,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, ligs, args.cpu_seconds)
