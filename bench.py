@@ -117,24 +117,36 @@ def summarize_counters(out_dir):
 
 
 def cpu_baseline(W, ligs, budget_s):
+    """The FP64 oracle on the host: the first ligands of the library for about budget_s seconds on all
+    threads OpenMP uses, then the first ligand alone on one thread."""
     import numpy as np
 
     import oracle
     pocket = W.pockets[0]
     log("cpu baseline: oracle grids")
     G = oracle.build_grids(pocket)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.get_threads()
     done, poses, t0 = 0, 0, time.perf_counter()
     n_rot = ligs.n_rot
+    pose_count = lambda i: W.search.n_starts * (1 + int(n_rot[i]) * (W.search.n_steps - 1))  # noqa: E731
     while time.perf_counter() - t0 < budget_s and done < ligs.n_lig:
         oracle.dock(pocket, G, ligs, W.search, sel=np.array([done]))
-        poses += W.search.n_starts * (1 + int(n_rot[done]) * (W.search.n_steps - 1))
+        poses += pose_count(done)
         done += 1
         log(f"cpu baseline: {done} ligands, {time.perf_counter() - t0:.1f} s")
     dt = time.perf_counter() - t0
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.dock(pocket, G, ligs, W.search, sel=np.array([0]))
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
+    log(f"cpu baseline: ligand 0 on one thread, {dt1:.1f} s")
     return {"value": done / dt, "unit": "ligands/s", "cores": cores, "kind": "oracle",
             "sample": f"first {done} ligands of the library, full search, FP64 oracle, grid build excluded",
-            "poses_per_sec": poses / dt, "seconds": round(dt, 2)}
+            "poses_per_sec": poses / dt, "seconds": round(dt, 2),
+            "one_core": {"value": 1 / dt1, "unit": "ligands/s", "poses_per_sec": pose_count(0) / dt1,
+                         "sample": "ligand 0 of the library, full search, one OpenMP thread",
+                         "seconds": round(dt1, 2)}}
 
 
 def prefilter_bench(args):

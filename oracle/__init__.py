@@ -322,6 +322,15 @@ def exhaustive(pocket, G, ligs, srch, l: int, periodic: bool = False):
 # Ranking and counting
 # ------------------------------------------------------------------------------------------------
 
+def set_threads(n: int) -> None:
+    """OpenMP threads of the batch entry points (dock, score_poses, ...)."""
+    _load().or_set_threads(ctypes.c_int(n))
+
+
+def get_threads() -> int:
+    return int(_load().or_get_threads())
+
+
 def topk(scores, k: int, ids=None):
     """The k lowest scores, ties to the lower id (NaN ranks as +inf)."""
     scores = np.asarray(scores, dtype=np.float64)

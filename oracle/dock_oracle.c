@@ -18,6 +18,7 @@
  * Units: Angstrom and kcal/mol-like energies; lower scores are better.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -741,3 +742,7 @@ int or_pose_coords(const or_library *lib, const or_search *s, int64_t l, int32_t
 
 void or_quat_matrix_c(const double *q, double *Rm) { or_quat_matrix(q, Rm); }
 void or_rodrigues_c(const double *u, double th, const double *v, double *out) { or_rodrigues(u, th, v, out); }
+
+/* Thread count of the batch entry points (OpenMP); not part of the method. */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_get_threads(void) { return omp_get_max_threads(); }
