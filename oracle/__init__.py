@@ -54,7 +54,8 @@ class Library(ctypes.Structure):
 class SearchC(ctypes.Structure):
     _fields_ = [("n_quat", ctypes.c_int32), ("quat", ctypes.POINTER(ctypes.c_float)),
                 ("n_trans", ctypes.c_int32), ("trans", ctypes.POINTER(ctypes.c_float)),
-                ("n_steps", ctypes.c_int32), ("clash_cut", ctypes.c_double), ("clash_w", ctypes.c_double)]
+                ("n_steps", ctypes.c_int32), ("clash_cut", ctypes.c_double), ("clash_w", ctypes.c_double),
+                ("sweep_top", ctypes.c_int32), ("passes", ctypes.c_int32)]
 
 
 _lib = None
@@ -119,7 +120,8 @@ def library(ligs) -> _Keep:
 def search(s) -> _Keep:
     q = np.ascontiguousarray(s.quat, dtype=np.float32)
     t = np.ascontiguousarray(s.trans, dtype=np.float32)
-    c = SearchC(len(q), _p(q, _F32), len(t), _p(t, _F32), int(s.n_steps), float(s.clash_cut), float(s.clash_w))
+    c = SearchC(len(q), _p(q, _F32), len(t), _p(t, _F32), int(s.n_steps), float(s.clash_cut), float(s.clash_w),
+                int(getattr(s, "sweep_top", 0)), int(getattr(s, "passes", 1)))
     return _Keep(c, q, t)
 
 

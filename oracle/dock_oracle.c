@@ -386,6 +386,8 @@ typedef struct {
     const float *trans; /* [n_trans][3] */
     int32_t n_steps;    /* S: torsion angles 2 pi s / S, s = 0..S-1 */
     double clash_cut, clash_w;
+    int32_t sweep_top;  /* 0: every start gets the torsion sweeps; K > 0: only the K best rigid starts */
+    int32_t passes;     /* greedy passes over the torsions (values below 1 count as 1) */
 } or_search;
 
 /*
@@ -434,10 +436,13 @@ void or_turn(const or_lig *L, const or_search *s, int k, int step, const double 
 }
 
 /*
- * One greedy pass from rigid start p: for each torsion in sweep order, score the
+ * Greedy search from rigid start p: for each torsion in sweep order, score the
  * conformer turned by every step, keep the lowest (ties to the lowest step), and
- * move on with that conformer.  Returns the final score.  steps[k] receives the
- * chosen steps; min_gap (may be NULL) the smallest relative decision gap met,
+ * move on with that conformer; the whole pass over the torsions is made s->passes
+ * times.  Returns the final score.  steps[k] receives torsion k's total turn, the sum
+ * of its chosen steps over the passes modulo S (a turn changes only its own torsion
+ * angle, so the final conformer is the reference one with each torsion turned once by
+ * its total); min_gap (may be NULL) the smallest relative decision gap met,
  * (second-lowest - lowest) / max(1, |lowest|), +inf if there was no decision.
  */
 double or_greedy(const or_lig *L, const or_frame *f, const float *G, const or_search *s, int p, int steps[],
@@ -445,7 +450,10 @@ double or_greedy(const or_lig *L, const or_frame *f, const float *G, const or_se
 {
     double X[OR_MAX_ATOMS][3], Y[OR_MAX_ATOMS][3], Best[OR_MAX_ATOMS][3];
     double gap = INFINITY;
+    const int passes = s->passes > 1 ? s->passes : 1;
     or_place(L, s, p, X);
+    for (int k = 0; k < L->B; ++k) steps[k] = 0;
+    for (int pass = 0; pass < passes; ++pass)
     for (int k = 0; k < L->B; ++k) {
         double e1 = INFINITY, e2 = INFINITY;
         int s1 = 0;
@@ -457,7 +465,7 @@ double or_greedy(const or_lig *L, const or_frame *f, const float *G, const or_se
         }
         double g = (e2 - e1) / (fabs(e1) > 1.0 ? fabs(e1) : 1.0);
         if (g < gap) gap = g;
-        steps[k] = s1;
+        steps[k] = (steps[k] + s1) % s->n_steps;
         memcpy(X, Best, sizeof(double) * 3 * L->n);
     }
     if (min_gap) *min_gap = gap;
@@ -530,12 +538,27 @@ static or_lig *load_selection(const or_library *lib, int32_t n_sel, const int64_
     return Ls;
 }
 
+/* Orders (score, start) pairs: lower score first, ties to the lower start. */
+typedef struct {
+    double e;
+    int32_t p;
+} or_keyed;
+
+static int or_keyed_cmp(const void *a, const void *b)
+{
+    const or_keyed *x = (const or_keyed *)a, *y = (const or_keyed *)b;
+    if (x->e < y->e) return -1;
+    if (x->e > y->e) return 1;
+    return (x->p > y->p) - (x->p < y->p);
+}
+
 /*
- * Docks the selected ligands.  For every rigid start the greedy pass is run
- * (the multiple restarts); the ligand's result is its best start, ties to the
- * lowest start index.  Ligands with a non-OK status get +inf and start -1.
- * Optional per-start outputs: finals [n_sel][Q*T], start_steps [n_sel][Q*T][16],
- * start_gap [n_sel][Q*T].
+ * Docks the selected ligands.  The greedy search is run from every rigid start (the
+ * multiple restarts), or, with s->sweep_top = K in [1, Q*T), only from the K starts
+ * whose rigid pose scores lowest (ties to the lower start); the ligand's result is its
+ * best searched start, ties to the lowest start index.  Ligands with a non-OK status
+ * get +inf and start -1.  Optional per-start outputs: finals [n_sel][Q*T] (+inf for
+ * starts not searched), start_steps [n_sel][Q*T][16], start_gap [n_sel][Q*T].
  */
 int or_dock(const or_frame *f, const float *G, const or_library *lib, const or_search *s, int32_t n_sel,
             const int64_t *sel, double *best, int32_t *best_p, int32_t *best_steps, int32_t *status,
@@ -543,13 +566,39 @@ int or_dock(const or_frame *f, const float *G, const or_library *lib, const or_s
 {
     or_lig *Ls = load_selection(lib, n_sel, sel);
     int64_t QT = (int64_t)s->n_quat * s->n_trans;
-    double *fin = (double *)malloc(sizeof(double) * (size_t)(n_sel * QT > 0 ? n_sel * QT : 1));
-    int32_t *stp = (int32_t *)malloc(sizeof(int32_t) * OR_MAX_TORS * (size_t)(n_sel * QT > 0 ? n_sel * QT : 1));
+    size_t cells = (size_t)(n_sel * QT > 0 ? n_sel * QT : 1);
+    double *fin = (double *)malloc(sizeof(double) * cells);
+    int32_t *stp = (int32_t *)malloc(sizeof(int32_t) * OR_MAX_TORS * cells);
+    uint8_t *searched = (uint8_t *)malloc(cells);
+    const int top = s->sweep_top > 0 && s->sweep_top < QT;
+    memset(searched, top ? 0 : 1, cells);
+    if (top) {
+        /* rigid scores of every start, then the K lowest per ligand */
+        or_keyed *rk = (or_keyed *)malloc(sizeof(or_keyed) * cells);
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t w = 0; w < (int64_t)n_sel * QT; ++w) {
+            int32_t i = (int32_t)(w / QT);
+            double X[OR_MAX_ATOMS][3];
+            rk[w].p = (int32_t)(w % QT);
+            rk[w].e = INFINITY;
+            if (Ls[i].status != OR_LIG_OK) continue;
+            or_place(&Ls[i], s, rk[w].p, X);
+            rk[w].e = or_score(&Ls[i], (const double(*)[3])X, f, G, s);
+        }
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int32_t i = 0; i < n_sel; ++i) {
+            qsort(rk + (size_t)i * QT, (size_t)QT, sizeof(or_keyed), or_keyed_cmp);
+            for (int k = 0; k < s->sweep_top; ++k) searched[(size_t)i * QT + rk[(size_t)i * QT + k].p] = 1;
+        }
+        free(rk);
+    }
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t w = 0; w < (int64_t)n_sel * QT; ++w) {
         int32_t i = (int32_t)(w / QT);
         int p = (int)(w % QT);
-        if (Ls[i].status != OR_LIG_OK) { fin[w] = INFINITY; continue; }
+        for (int k = 0; k < OR_MAX_TORS; ++k) stp[w * OR_MAX_TORS + k] = 0;
+        if (start_gap) start_gap[w] = INFINITY;
+        if (Ls[i].status != OR_LIG_OK || !searched[w]) { fin[w] = INFINITY; continue; }
         int steps[OR_MAX_TORS] = {0};
         double gap;
         fin[w] = or_greedy(&Ls[i], f, G, s, p, steps, &gap);
@@ -570,6 +619,7 @@ int or_dock(const or_frame *f, const float *G, const or_library *lib, const or_s
         if (start_steps) memcpy(start_steps + i * QT * OR_MAX_TORS, stp + i * QT * OR_MAX_TORS,
                                 sizeof(int32_t) * OR_MAX_TORS * (size_t)QT);
     }
+    free(searched);
     free(stp);
     free(fin);
     free(Ls);

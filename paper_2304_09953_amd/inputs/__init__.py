@@ -254,6 +254,8 @@ class Search:
     n_steps: int
     clash_cut: float = 2.5
     clash_w: float = 10.0
+    sweep_top: int = 0    # 0: every start gets the torsion sweeps; K: only the K best rigid starts
+    passes: int = 1       # greedy passes over the torsions
 
     @property
     def n_starts(self) -> int:
@@ -330,4 +332,4 @@ def mlp_init(d_in: int = 512, h1: int = 1024, h2: int = 1024, seed: int = BASE_S
 def search_for(pocket: Pocket, base: Search, radius: float = 4.0) -> Search:
     """The same search centred on another pocket (translations follow the pocket centre)."""
     return Search(base.quat, translations(len(base.trans), radius, pocket.center), base.n_steps,
-                  base.clash_cut, base.clash_w)
+                  base.clash_cut, base.clash_w, base.sweep_top, base.passes)
