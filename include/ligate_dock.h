@@ -57,6 +57,8 @@ extern "C" {
 #define DOCK_MAX_TORSIONS 16
 #define DOCK_MAX_TYPES 32
 #define DOCK_MAX_STEPS 1024
+#define DOCK_MAX_TOP_STARTS 8192 /* starts ranked per ligand when sweep_top selects */
+#define DOCK_MAX_PASSES 16
 
 #define DOCK_LAYOUT_LINEAR 0     /* grids [t][z][y][x], FP32, x fastest */
 #define DOCK_LAYOUT_XY4 1        /* per node a 16-byte record of its z plane: G(x, y),
@@ -97,8 +99,13 @@ typedef struct {
 /*
  * Pose search.  Rigid start p = iq * n_trans + it places the centred ligand
  * with quaternion d_quat[iq] (w, x, y, z; normalised by the library) and
- * translation d_trans[it]; then one greedy pass turns each torsion, in sweep
- * order, by the best of the n_steps angles 2 pi s / n_steps.
+ * translation d_trans[it]; then a greedy pass turns each torsion, in sweep
+ * order, by the best of the n_steps angles 2 pi s / n_steps.  Search budget:
+ * with sweep_top = K in [1, n_quat*n_trans) only the K starts whose rigid pose
+ * scores lowest (FP32, ties to the lower start) get the greedy passes, which
+ * needs n_quat*n_trans <= DOCK_MAX_TOP_STARTS; 0 or K >= n_quat*n_trans
+ * searches from every start.  passes (0 or 1 = one; at most DOCK_MAX_PASSES)
+ * repeats the pass over the torsions.
  */
 typedef struct {
     int32_t n_quat;
@@ -110,6 +117,8 @@ typedef struct {
     float clash_w;        /* clash weight: clash_w * (clash_cut - d)^2 */
     int32_t starts_per_item; /* rigid starts per work item; 0 = chosen by the library */
     int32_t waves_per_block; /* 1, 2, 4 or 8; 0 = chosen by the library */
+    int32_t sweep_top;       /* 0 = every start; K = the K best rigid starts */
+    int32_t passes;          /* greedy passes over the torsions; 0 = 1 */
 } dock_search;
 
 /* Size in bytes of the grids for descriptor g. */
@@ -147,17 +156,21 @@ int dock_pack_ligands(const int32_t *d_atom_off, const float *d_xyz, const uint8
                       void *stream);
 
 /*
- * Docks every packed ligand: all rigid starts, each followed by one greedy
- * torsion pass; per ligand the lowest final score wins, ties to the lowest
- * start.  Outputs, indexed by the ligand's position in the packed library:
- * d_best_score [n_lig] (+inf for a ligand whose status is not OK),
- * d_best_start [n_lig] (-1 if not OK), d_best_steps [n_lig][16] (the chosen
- * step of each torsion in sweep order, unused entries 0), optional
- * d_start_scores [n_lig][n_quat*n_trans] (final score of every start; NULL to
- * skip), optional d_start_steps [n_lig][n_quat*n_trans][16] (the steps every
- * start chose; NULL to skip), optional d_pose_count [1] (distinct poses scored:
- * per docked ligand n_quat*n_trans*(1 + B*(n_steps-1))).  n_lig and n_atoms_total must match the
- * pack.  Workspace: query with d_ws == NULL.
+ * Docks every packed ligand: the rigid starts (all, or the sweep_top best),
+ * each followed by the greedy torsion passes; per ligand the lowest final score
+ * wins, ties to the lowest start.  Outputs, indexed by the ligand's position in
+ * the packed library: d_best_score [n_lig] (+inf for a ligand whose status is
+ * not OK), d_best_start [n_lig] (-1 if not OK), d_best_steps [n_lig][16] (each
+ * torsion's total turn in sweep order: the sum of its chosen steps over the
+ * passes, modulo n_steps; a turn changes only its own torsion angle, so the
+ * final pose is the start with each torsion turned once by its total; unused
+ * entries 0), optional d_start_scores [n_lig][n_quat*n_trans] (final score of
+ * every searched start, +inf for starts not searched; NULL to skip), optional
+ * d_start_steps [n_lig][n_quat*n_trans][16] (every searched start's totals;
+ * NULL to skip), optional d_pose_count [1] (distinct poses scored: per docked
+ * ligand n_quat*n_trans*(1 + passes*B*(n_steps-1)), or with sweep_top = K,
+ * n_quat*n_trans + K*passes*B*(n_steps-1)).  n_lig and n_atoms_total must match
+ * the pack.  Workspace: query with d_ws == NULL.
  */
 int dock_screen(const dock_grid_desc *g, const float *d_grids, const void *d_pack, int32_t n_lig,
                 int64_t n_atoms_total, const dock_search *s, float *d_best_score, int32_t *d_best_start,

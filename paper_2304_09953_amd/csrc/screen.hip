@@ -59,6 +59,8 @@ struct SearchC {
     float cut, cut2, cut2_keep, w;  // clash in grid units: cut-off / h, its square, (cut-off / h + margin)^2,
                                     // weight h^2
     float sw, swc;                  // sqrt(w) and sqrt(w) cut
+    int top;                        // starts searched per ligand when they are selected (0: all)
+    int passes;                     // greedy passes over the torsions (>= 1)
 };
 
 // Coordinates inside a start are in grid units (x - origin) / spacing throughout: the map is a
@@ -416,8 +418,8 @@ __device__ float direct_score(const GridC &g, rsrc_t rs, const SearchC &s, const
     return wave_sum(acc);
 }
 
-// One greedy pass from rigid start p.  Returns the final score (identical on all lanes);
-// lane k (< B) receives the step chosen for torsion k in `my_step`.
+// The greedy passes from rigid start p.  Returns the final score (identical on all lanes);
+// lane k (< B) receives torsion k's total turn over the passes (modulo S) in `my_step`.
 template <int APL, int BOUNDARY, int LAYOUT>
 __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const LigLDS &L, WaveLDS &W, int p,
                            float clash_ref, const float (&cs)[APL], const float (&sn)[APL], int &my_step) {
@@ -442,7 +444,9 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
     constexpr int NA = 4 / NJ;
     const float edge = 1e-3f;  // margin of the inside-the-box test, in grid units
 
-    for (int k = 0; k < L.B; ++k) {
+    my_step = 0;
+    // the sweeps of all passes: torsion k runs 0..B-1 in every pass
+    for (int sweep = 0, k = 0; sweep < s.passes * L.B; ++sweep, k = k + 1 == L.B ? 0 : k + 1) {
         const TorRec tr = L.tor[k];
         const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
         float xax, xay, xaz, ux, uy, uz;
@@ -650,7 +654,10 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
                 cz[h] = fmaf(az, cb, fmaf(bz, sb, pz));
             }
         }
-        if (lane == k) my_step = sbest;
+        if (lane == k) {  // total turn of torsion k over the passes, modulo S
+            my_step += sbest;
+            my_step -= my_step >= s.S ? s.S : 0;
+        }
     }
     if (Emax > 16.0f * fmaxf(1.0f, fabsf(E))) E = direct_score<BOUNDARY, LAYOUT>(g, rs, s, L, cx, cy, cz);
     return E;
@@ -669,6 +676,7 @@ struct ScreenArgs {
     uint32_t *counter;
     float *start_scores;     // optional [n_lig][QT]
     uint16_t *start_steps;   // optional [n_lig][QT][16]
+    const uint32_t *sel;     // [n_lig][s.top] starts to search when s.top > 0
     int n_lig, P, bpl, nw;
     int64_t n_items;
 };
@@ -682,16 +690,18 @@ __global__ void k_screen_init(uint64_t *best_key, int n_lig, uint32_t *counter, 
     }
 }
 
-// Planner: cost-descending order (ties by ligand index); invalid ligands last.
-__global__ void k_screen_plan(const LigDesc *desc, int n_lig, int S, uint64_t *keys, uint64_t *pose_count, int QT) {
+// Planner: cost-descending order (ties by ligand index); invalid ligands last.  Poses: every
+// rigid start once, plus (S - 1) new poses per torsion sweep of each searched start.
+__global__ void k_screen_plan(const LigDesc *desc, int n_lig, int S, uint64_t *keys, uint64_t *pose_count, int QT,
+                              int n_searched, int passes) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t poses = 0;
     if (l < n_lig) {
         const LigDesc d = desc[l];
         uint64_t cost = 0;
         if (d.status == DOCK_LIG_OK) {
-            cost = (uint64_t)d.n + (uint64_t)(S - 1) * (uint64_t)d.sum_m + (uint64_t)d.n_pairs;
-            poses = (uint64_t)QT * (1ull + (uint64_t)d.B * (uint64_t)(S - 1));
+            cost = (uint64_t)d.n + (uint64_t)passes * ((uint64_t)(S - 1) * (uint64_t)d.sum_m + (uint64_t)d.n_pairs);
+            poses = (uint64_t)QT + (uint64_t)n_searched * (uint64_t)passes * (uint64_t)d.B * (uint64_t)(S - 1);
         }
         if (cost > 0xffffffffull) cost = 0xffffffffull;
         keys[l] = ((uint64_t)(~(uint32_t)cost) << 32) | (uint32_t)l;
@@ -703,6 +713,111 @@ __global__ void k_screen_plan(const LigDesc *desc, int n_lig, int S, uint64_t *k
         for (int src = 0; src < kWave; ++src)
             tot += ((uint64_t)(uint32_t)__shfl((int)hi, src) << 32) | (uint32_t)__shfl((int)lo, src);
         if (lane_id() == 0 && tot) atomicAdd((unsigned long long *)pose_count, (unsigned long long)tot);
+    }
+}
+
+constexpr int kTopBlock = 256;
+
+// Exclusive prefix sum over the kTopBlock threads of a block (thread order); `scratch` holds one
+// value per wavefront.  All threads must call it.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *scratch) {
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    uint32_t inc = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
+        if (lane >= off) inc += o;
+    }
+    if (lane == kWave - 1) scratch[w] = inc;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int q = 0; q < w; ++q) base += scratch[q];
+    __syncthreads();
+    return base + inc - v;
+}
+
+// Search budget: the rigid score of every start of one ligand (the same arithmetic as the screen's
+// rigid placement), then the K lowest, ties to the lower start, by a radix select over the ordered
+// 32-bit scores (a start's index is its position).  Writes the chosen starts in increasing order to
+// sel[lig][K]; with start_scores given, first sets every start's entry to +inf (the screen then
+// writes the searched ones).
+template <int BOUNDARY, int LAYOUT>
+__global__ __launch_bounds__(kTopBlock) void k_rigid_top(ScreenArgs A, uint32_t *sel) {
+    extern __shared__ __align__(16) char smem[];
+    LigLDS &L = *reinterpret_cast<LigLDS *>(smem);
+    uint32_t *key = reinterpret_cast<uint32_t *>(smem + ((sizeof(LigLDS) + 15) & ~size_t(15)));  // [QT]
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t scan_s[2][kTopBlock / kWave];
+    __shared__ uint32_t prefix_s, need_s;
+    __shared__ float clash_s;
+    const int lig = blockIdx.x, tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    const int QT = A.s.QT, K = A.s.top;
+    load_ligand(L, A.pk, lig, A.g, tid, kTopBlock);
+    if (A.start_scores)
+        for (int p = tid; p < QT; p += kTopBlock) A.start_scores[(size_t)lig * QT + p] = INFINITY;
+    __syncthreads();
+    if (L.status != DOCK_LIG_OK) return;  // block-uniform
+    if (w == 0) {
+        const float c = rigid_clash(L, A.s);
+        if (lane == 0) clash_s = c;
+    }
+    __syncthreads();
+    const float clash_ref = clash_s;
+    const rsrc_t rs = grid_rsrc(A.g);
+    for (int p = w; p < QT; p += kTopBlock / kWave) {
+        float cx[2], cy[2], cz[2];
+        place(A.g, A.s, L, p, cx, cy, cz);
+        float eg = 0.0f;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = lane + kWave * h;
+            if (i < L.n) eg += lookup_lane<BOUNDARY, LAYOUT>(A.g, rs, L.tof[i], cx[h], cy[h], cz[h]);
+        }
+        const float E = wave_sum(eg) + clash_ref;
+        if (lane == 0) key[p] = float_to_ordered(E);
+    }
+    __syncthreads();
+    // the K-th smallest key, eight bits at a time from the top; `need` of the keys equal to it
+    // belong to the K lowest
+    uint32_t prefix = 0, mask = 0, need = (uint32_t)K;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hist[tid] = 0u;
+        __syncthreads();
+        for (int p = tid; p < QT; p += kTopBlock) {
+            const uint32_t k = key[p];
+            if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t acc = 0, d = 0;
+            for (; d < 255u; ++d) {
+                if (acc + hist[d] >= need) break;
+                acc += hist[d];
+            }
+            need_s = need - acc;
+            prefix_s = prefix | (d << shift);
+        }
+        __syncthreads();
+        need = need_s;
+        prefix = prefix_s;
+        mask |= 255u << shift;
+        __syncthreads();
+    }
+    // order-preserving compaction: thread t owns the starts [t chunk, (t + 1) chunk)
+    const int chunk = (QT + kTopBlock - 1) / kTopBlock;
+    const int b0 = min(tid * chunk, QT), b1 = min(b0 + chunk, QT);
+    uint32_t n_less = 0, n_eq = 0;
+    for (int p = b0; p < b1; ++p) {
+        n_less += key[p] < prefix;
+        n_eq += key[p] == prefix;
+    }
+    uint32_t less = block_exclusive_scan(n_less, scan_s[0]);
+    uint32_t eq = block_exclusive_scan(n_eq, scan_s[1]);
+    for (int p = b0; p < b1; ++p) {
+        const uint32_t k = key[p];
+        if (k < prefix || (k == prefix && eq < need)) sel[(size_t)lig * K + less + min(eq, need)] = (uint32_t)p;
+        less += k < prefix;
+        eq += k == prefix;
     }
 }
 
@@ -731,8 +846,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (L.status == DOCK_LIG_OK) {
             const float clash_ref = rigid_clash(L, A.s);
             uint64_t wbest = ~0ull;
-            const int p0 = batch * A.P, p1 = min(p0 + A.P, A.s.QT);
-            for (int p = p0 + w; p < p1; p += A.nw) {
+            const int p0 = batch * A.P, p1 = min(p0 + A.P, A.s.top ? A.s.top : A.s.QT);
+            for (int idx = p0 + w; idx < p1; idx += A.nw) {
+                const int p = A.s.top ? (int)A.sel[(size_t)lig * A.s.top + idx] : idx;
                 int step = 0;
                 const float E = run_start<APL, BOUNDARY, LAYOUT>(A.g, rs, A.s, L, W, p, clash_ref, cs, sn, step);
                 const uint64_t key = ((uint64_t)float_to_ordered(E) << 32) | (uint32_t)p;
@@ -876,6 +992,11 @@ static int check_search(const dock_search *s) {
     LIGATE_REQUIRE(s->clash_cut >= 0.0f && s->clash_w >= 0.0f, DOCK_ERR_INVALID_ARG, "negative clash parameters");
     LIGATE_REQUIRE(s->starts_per_item >= 0 && s->waves_per_block >= 0 && s->waves_per_block <= 8,
                    DOCK_ERR_INVALID_ARG, "bad tuning fields");
+    LIGATE_REQUIRE(s->sweep_top >= 0 && s->passes >= 0 && s->passes <= DOCK_MAX_PASSES, DOCK_ERR_INVALID_ARG,
+                   "sweep_top must be >= 0 and passes in [0, %d]", DOCK_MAX_PASSES);
+    LIGATE_REQUIRE(s->sweep_top == 0 || s->sweep_top >= (int64_t)s->n_quat * s->n_trans ||
+                       (int64_t)s->n_quat * s->n_trans <= DOCK_MAX_TOP_STARTS,
+                   DOCK_ERR_LIMIT, "selecting sweep_top starts needs n_quat * n_trans <= %d", DOCK_MAX_TOP_STARTS);
     return DOCK_OK;
 }
 
@@ -895,6 +1016,8 @@ static SearchC make_search(const dock_search *d, float spacing) {
     s.w = d->clash_w * spacing * spacing;
     s.sw = sqrtf(s.w);
     s.swc = s.sw * s.cut;
+    s.top = d->sweep_top > 0 && d->sweep_top < s.QT ? d->sweep_top : 0;
+    s.passes = d->passes > 1 ? d->passes : 1;
     return s;
 }
 
@@ -904,6 +1027,11 @@ static size_t screen_lds(int nw) { return ((sizeof(LigLDS) + 15) & ~size_t(15)) 
 
 template <int APL, int BOUNDARY, int LAYOUT>
 static int launch_screen(const ScreenArgs &A, float *bs, int32_t *bp, uint16_t *bst, hipStream_t st) {
+    if (A.s.top) {
+        const size_t lds = ((sizeof(LigLDS) + 15) & ~size_t(15)) + 4 * (size_t)A.s.QT;
+        hipLaunchKernelGGL((k_rigid_top<BOUNDARY, LAYOUT>), dim3((unsigned)A.n_lig), dim3(kTopBlock), lds, st, A,
+                           const_cast<uint32_t *>(A.sel));
+    }
     static int cu = 0;
     if (cu == 0) {
         int dev = 0;
@@ -963,7 +1091,9 @@ extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const
     LIGATE_REQUIRE(n_lig >= 1 && n_atoms_total >= 0 && n_atoms_total < (1ll << 31), DOCK_ERR_INVALID_ARG,
                    "bad library size");
     LIGATE_REQUIRE(ws_bytes != nullptr, DOCK_ERR_INVALID_ARG, "ws_bytes is NULL");
-    const size_t need = al(8 * (size_t)n_lig) + al(8 * (size_t)n_lig) + al(256) + radix_sort_ws_bytes(n_lig);
+    const SearchC sc = make_search(sd, gd->spacing);
+    const size_t sel_bytes = sc.top ? al(4 * (size_t)n_lig * (size_t)sc.top) : 0;
+    const size_t need = al(8 * (size_t)n_lig) + al(8 * (size_t)n_lig) + al(256) + sel_bytes + radix_sort_ws_bytes(n_lig);
     if (d_ws == nullptr) {
         *ws_bytes = need;
         return DOCK_OK;
@@ -976,13 +1106,15 @@ extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const
     uint64_t *best_key = (uint64_t *)w;
     uint64_t *order = (uint64_t *)(w + al(8 * (size_t)n_lig));
     uint32_t *counter = (uint32_t *)(w + 2 * al(8 * (size_t)n_lig));
-    void *rws = w + 2 * al(8 * (size_t)n_lig) + al(256);
+    uint32_t *sel = sc.top ? (uint32_t *)(w + 2 * al(8 * (size_t)n_lig) + al(256)) : nullptr;
+    void *rws = w + 2 * al(8 * (size_t)n_lig) + al(256) + sel_bytes;
 
     ScreenArgs A;
     A.g = make_grid(gd, d_grids);
     A.g.G = d_grids;
-    A.s = make_search(sd, gd->spacing);
+    A.s = sc;
     A.pk = PackView::of(d_pack, n_lig, n_atoms_total);
+    A.sel = sel;
     A.order = order;
     A.best_key = best_key;
     A.counter = counter;
@@ -996,20 +1128,21 @@ extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const
     if (P == 0) {
         // enough items to keep every block busy several times over, at most 256 starts per item
         const int64_t slots = (int64_t)default_cu_count() * 6;
-        const int64_t total = (int64_t)n_lig * A.s.QT;
+        const int64_t total = (int64_t)n_lig * (A.s.top ? A.s.top : A.s.QT);
         int64_t want = total / (4 * slots);
         want = std::max<int64_t>(A.nw, std::min<int64_t>(256, want));
         P = (int)want;
     }
-    P = std::min(P, A.s.QT);
+    const int n_searched = A.s.top ? A.s.top : A.s.QT;
+    P = std::min(P, n_searched);
     A.P = P;
-    A.bpl = (A.s.QT + P - 1) / P;
+    A.bpl = (n_searched + P - 1) / P;
     A.n_items = (int64_t)n_lig * A.bpl;
 
     const unsigned nb = (unsigned)((n_lig + 255) / 256);
     hipLaunchKernelGGL(k_screen_init, dim3(nb), dim3(256), 0, st, best_key, n_lig, counter, d_pose_count);
     hipLaunchKernelGGL(k_screen_plan, dim3(nb), dim3(256), 0, st, A.pk.desc, n_lig, A.s.S, order, d_pose_count,
-                       A.s.QT);
+                       A.s.QT, n_searched, A.s.passes);
     rc = radix_sort_u64(order, n_lig, 32, 64, rws, st);
     if (rc) return rc;
     if (gd->layout == DOCK_LAYOUT_XY4)

@@ -49,7 +49,7 @@ class SearchDesc(ctypes.Structure):
     _fields_ = [("n_quat", ctypes.c_int32), ("d_quat", ctypes.c_void_p), ("n_trans", ctypes.c_int32),
                 ("d_trans", ctypes.c_void_p), ("n_steps", ctypes.c_int32), ("clash_cut", ctypes.c_float),
                 ("clash_w", ctypes.c_float), ("starts_per_item", ctypes.c_int32),
-                ("waves_per_block", ctypes.c_int32)]
+                ("waves_per_block", ctypes.c_int32), ("sweep_top", ctypes.c_int32), ("passes", ctypes.c_int32)]
 
 
 class DockError(RuntimeError):
@@ -112,9 +112,11 @@ def grid_desc(pocket, boundary: int = BOUNDARY_CLAMP, layout: int = LAYOUT_XY4) 
 
 
 def search_desc(d_quat: torch.Tensor, d_trans: torch.Tensor, n_steps: int, clash_cut: float = 2.5,
-                clash_w: float = 10.0, starts_per_item: int = 0, waves_per_block: int = 0) -> SearchDesc:
+                clash_w: float = 10.0, starts_per_item: int = 0, waves_per_block: int = 0, sweep_top: int = 0,
+                passes: int = 1) -> SearchDesc:
     return SearchDesc(d_quat.shape[0], d_quat.data_ptr(), d_trans.shape[0], d_trans.data_ptr(), int(n_steps),
-                      float(clash_cut), float(clash_w), int(starts_per_item), int(waves_per_block))
+                      float(clash_cut), float(clash_w), int(starts_per_item), int(waves_per_block), int(sweep_top),
+                      int(passes))
 
 
 # ------------------------------------------------------------------------------------------------

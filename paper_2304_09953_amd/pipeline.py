@@ -104,7 +104,7 @@ class DeviceSearch:
         self.quat = _dev(search.quat, device, torch.float32)
         self.trans = _dev(search.trans, device, torch.float32)
         self.desc = dock.search_desc(self.quat, self.trans, search.n_steps, search.clash_cut, search.clash_w,
-                                     starts_per_item, waves_per_block)
+                                     starts_per_item, waves_per_block, search.sweep_top, search.passes)
 
     @property
     def n_starts(self) -> int:

@@ -131,6 +131,22 @@ def test_size_queries_and_argument_errors():
     s_bad = dock.SearchDesc(4, fake, 2, fake, 2048, 2.5, 10.0, 0, 0)
     assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(s_bad), None, None, None, None,
                            None, None, None, ctypes.byref(sz), None) == -2
+    # search budget: the selection adds n_lig x K start ids to the workspace; bad fields are refused
+    base = sz.value
+    s_top = dock.SearchDesc(4, fake, 2, fake, 64, 2.5, 10.0, 0, 0, 3, 2)
+    assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(s_top), None, None, None, None,
+                           None, None, None, ctypes.byref(sz), None) == 0
+    assert sz.value >= base + 10 * 3 * 4
+    for top, passes, code in ((-1, 1, -1), (0, -1, -1), (0, 17, -1), (4, 1, 0), (8, 16, 0)):
+        sb = dock.SearchDesc(4, fake, 2, fake, 64, 2.5, 10.0, 0, 0, top, passes)
+        assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(sb), None, None, None,
+                               None, None, None, None, ctypes.byref(sz), None) == code, (top, passes)
+    many = dock.SearchDesc(4096, fake, 4, fake, 64, 2.5, 10.0, 0, 0, 100, 1)  # 16384 starts to rank
+    assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(many), None, None, None, None,
+                           None, None, None, ctypes.byref(sz), None) == -2
+    all_of_many = dock.SearchDesc(4096, fake, 4, fake, 64, 2.5, 10.0, 0, 0, 16384, 1)  # nothing to select
+    assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(all_of_many), None, None,
+                           None, None, None, None, None, ctypes.byref(sz), None) == 0
     assert lib.dock_topk(None, None, 100, 10, None, None, None, ctypes.byref(sz), None) == 0
     assert lib.dock_topk(None, None, 100, 101, None, None, None, ctypes.byref(sz), None) == -1
     assert lib.dock_topk(None, None, 0, 1, None, None, None, ctypes.byref(sz), None) == -1
