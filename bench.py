@@ -216,6 +216,56 @@ def prefilter_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def budget_curve(args):
+    """Speed and quality of the search-budget variants against the full search on the first
+    args.n_lig (default 20000) ligands of the 100k workload: ligands/s, and per variant the mean
+    and worst score loss against the full search and the share of the full search's top 1 % that
+    the variant's own top 1 % keeps."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2304_09953_amd import inputs as I
+    from paper_2304_09953_amd import pipeline as P
+    W = I.workload("pocket96-lib100k")
+    n_lig = args.n_lig or 20000
+    ligs = W.ligands(n_lig=n_lig)
+    dp = P.DevicePocket(W.pockets[0])
+    lib = P.DeviceLibrary(ligs)
+    variants = [(0, 1), (0, 2), (1024, 1), (256, 1), (256, 2), (64, 1), (64, 2), (16, 1), (4, 1), (1, 1)]
+    rows, ref = [], None
+    for top, passes in variants:
+        srch = dataclasses.replace(W.search, sweep_top=top, passes=passes)
+        scr = P.Screener(dp, lib, P.DeviceSearch(srch))
+        scr.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        scr.run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = scr.best_score.cpu().numpy().astype(np.float64)
+        poses = int(scr.pose_count.cpu().item())
+        if ref is None:
+            ref = best
+        ok = np.isfinite(ref)
+        loss = (best - ref)[ok]
+        k = max(1, int(round(0.01 * ok.sum())))
+        top_ref = set(np.flatnonzero(ok)[np.lexsort((np.flatnonzero(ok), ref[ok]))[:k]].tolist())
+        top_var = set(np.flatnonzero(ok)[np.lexsort((np.flatnonzero(ok), best[ok]))[:k]].tolist())
+        rows.append({"sweep_top": top, "passes": passes, "screen_ms": ms, "ligands_per_s": n_lig / (ms * 1e-3),
+                     "poses_per_s": poses / (ms * 1e-3), "mean_score_change": float(loss.mean()),
+                     "worst_score_change": float(loss.max()), "best_of_full_or_better": float(np.mean(loss <= 1e-4 * np.maximum(1, np.abs(ref[ok])))),
+                     "top1pct_overlap_with_full": len(top_ref & top_var) / k})
+        log(f"sweep_top={top} passes={passes}: {ms:.0f} ms, {n_lig / (ms * 1e-3):.0f} ligands/s, "
+            f"mean change {loss.mean():+.3f}, top-1% overlap {len(top_ref & top_var) / k:.3f}")
+    print(json.dumps({"metric": "search-budget speed/quality curve", "unit": "ligands/s",
+                      "config": {"workload": f"first {n_lig} ligands of {W.name}", "reference": "sweep_top=0, passes=1"},
+                      "rows": rows}), flush=True)
+
+
 def calibrate_peaks(args):
     """Measured peaks of this GPU: non-packed FP32 FMA rate and read bandwidth of a buffer resident
     in the L2 caches (2 MiB, read by every block) and of one resident in the Infinity Cache only
@@ -282,6 +332,9 @@ def main():
                     help="write the screen's counter summary from rocprofv3 --pmc CSV directories in DIR")
     ap.add_argument("--calibrate-peaks", choices=("all", "l2", "mall", "fma"), default=None,
                     help="measure the FMA rate and cache-resident read bandwidth of this GPU, then exit")
+    ap.add_argument("--budget-curve", action="store_true",
+                    help="speed and quality of the search-budget variants (sweep_top, passes) against the full "
+                         "search on --n-lig ligands (default 20000)")
     ap.add_argument("--layout", choices=("xy4", "linear"), default="xy4",
                     help="grid layout: 16-byte records of the four xy neighbours, or plain [t][z][y][x]")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -327,6 +380,8 @@ def main():
     dock.load()  # fails loudly if the HIP library is missing
     if args.calibrate_peaks:
         return calibrate_peaks(args)
+    if args.budget_curve:
+        return budget_curve(args)
     if args.prefilter:
         return prefilter_bench(args)
     W = I.workload("pocket96-lib100k")
