@@ -216,7 +216,7 @@ def chunk_shape_for(ligs, idx: np.ndarray, chunk: int) -> ChunkShape:
 
 
 def screen_buckets(pocket_dev, search, ligs, k: int = 1000, chunk: int = 16384, tuned: bool = True,
-                   use_graph: bool = True, log=None):
+                   use_graph: bool = True, log=None, table_path: str | None = None):
     """Screens a library against one pocket bucket by bucket in graph-replayed chunks, merging
     into one running top-k.  Returns (top scores, top global ids, per-ligand best scores)."""
     arch = arch_name()
@@ -228,7 +228,7 @@ def screen_buckets(pocket_dev, search, ligs, k: int = 1000, chunk: int = 16384, 
         idx = np.flatnonzero(buckets == bucket)
         if len(idx) == 0:
             continue
-        p, w = lookup(arch, pocket_dev.pocket.dims, search.n_steps, bucket) if tuned else (0, 0)
+        p, w = lookup(arch, pocket_dev.pocket.dims, search.n_steps, bucket, table_path) if tuned else (0, 0)
         pipe = ChunkPipeline(pocket_dev, search, chunk_shape_for(ligs, idx, chunk), ligs.n_types, k, p, w, use_graph)
         pipe.reset()
         pipe.scores[:k].copy_(torch.from_numpy(top_s))
