@@ -186,6 +186,17 @@ int dock_topk(const float *d_scores, const int32_t *d_ids, int64_t n, int32_t k,
               int32_t *d_out_ids, void *d_ws, size_t *ws_bytes, void *stream);
 
 /*
+ * Ranking over several binding sites (a ligand is as good as its best site):
+ * d_scores [n_pockets][n] holds, row by row, dock_screen's d_best_score of the
+ * same n ligands against each pocket; NaN counts as +inf.  d_best [n] receives
+ * each ligand's lowest score and d_pocket [n] the row it came from (ties to the
+ * lower row; -1 when every score is +inf).  dock_topk over d_best then ranks
+ * the library.  1 <= n_pockets <= 1024, 1 <= n < 2^31.  No workspace.
+ */
+int dock_merge_pockets(const float *d_scores, int32_t n_pockets, int64_t n, float *d_best, int32_t *d_pocket,
+                       void *stream);
+
+/*
  * Scores explicit poses from scratch (no incremental bookkeeping): pose i is
  * ligand d_lig[i] placed at rigid start d_start[i], then torsion k (sweep
  * order) turned by step d_steps[i][k] for k < B.  d_steps is [n_poses][16].

@@ -188,17 +188,6 @@ __device__ __forceinline__ int wave_sum_i(int v) {
     return v;
 }
 
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, off);
-        uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), off);
-        uint64_t o = ((uint64_t)hi << 32) | lo;
-        v = o < v ? o : v;
-    }
-    return v;
-}
-
 // Number of set bits of a 64-bit lane mask below this lane.
 __device__ __forceinline__ int lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));

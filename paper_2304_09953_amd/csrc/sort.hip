@@ -164,3 +164,35 @@ extern "C" int dock_topk(const float *d_scores, const int32_t *d_ids, int64_t n,
                        d_out_ids);
     return check_launch("dock_topk");
 }
+
+namespace ligate {
+
+__global__ void k_merge_pockets(const float *__restrict__ scores, int n_pockets, int64_t n, float *best,
+                                int32_t *pocket) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float b = INFINITY;
+    int bp = -1;
+    for (int p = 0; p < n_pockets; ++p) {
+        float v = scores[(int64_t)p * n + i];
+        v = v != v ? INFINITY : v;
+        if (v < b) {
+            b = v;
+            bp = p;
+        }
+    }
+    best[i] = b;
+    pocket[i] = bp;
+}
+
+}  // namespace ligate
+
+extern "C" int dock_merge_pockets(const float *d_scores, int32_t n_pockets, int64_t n, float *d_best,
+                                  int32_t *d_pocket, void *stream) {
+    LIGATE_REQUIRE(n_pockets >= 1 && n_pockets <= 1024, DOCK_ERR_INVALID_ARG, "n_pockets must be in [1, 1024]");
+    LIGATE_REQUIRE(n >= 1 && n < (1ll << 31), DOCK_ERR_INVALID_ARG, "n must be in [1, 2^31)");
+    LIGATE_REQUIRE(d_scores && d_best && d_pocket, DOCK_ERR_INVALID_ARG, "NULL array");
+    hipLaunchKernelGGL(ligate::k_merge_pockets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       d_scores, n_pockets, n, d_best, d_pocket);
+    return ligate::check_launch("dock_merge_pockets");
+}

@@ -28,7 +28,7 @@ LIG_STATUS = {0: "ok", 1: "n_atoms", 2: "type", 3: "n_bonds", 4: "bond_index", 5
               7: "terminal_rotatable", 8: "n_torsions"}
 
 EXPORTS = ("dock_grid_bytes", "dock_build_grids", "dock_pack_ligands", "dock_screen", "dock_topk",
-           "dock_score_poses", "dock_error_string", "dock_last_error")
+           "dock_merge_pockets", "dock_score_poses", "dock_error_string", "dock_last_error")
 
 
 class GridDesc(ctypes.Structure):
@@ -73,6 +73,7 @@ def load() -> ctypes.CDLL:
         lib.dock_screen.argtypes = [P(GridDesc), vp, vp, i32, i64, P(SearchDesc), vp, vp, vp, vp, vp, vp, vp, P(sz), vp]
         lib.dock_topk.argtypes = [vp, vp, i64, i32, vp, vp, vp, P(sz), vp]
         lib.dock_score_poses.argtypes = [P(GridDesc), vp, vp, i32, i64, P(SearchDesc), vp, vp, vp, i64, vp, vp]
+        lib.dock_merge_pockets.argtypes = [vp, i32, i64, vp, vp, vp]
         lib.dock_error_string.restype = ctypes.c_char_p
         lib.dock_error_string.argtypes = [ctypes.c_int]
         lib.dock_last_error.restype = ctypes.c_char_p
@@ -189,6 +190,12 @@ def score_poses(desc: GridDesc, grids, pack, n_lig: int, n_atoms: int, search: S
     _check(load().dock_score_poses(ctypes.byref(desc), _ptr(grids), _ptr(pack), n_lig, n_atoms, ctypes.byref(search),
                                    _ptr(lig), _ptr(start), _ptr(steps), lig.numel(), _ptr(out), _stream(stream)),
            "dock_score_poses")
+
+
+def merge_pockets(scores: torch.Tensor, best: torch.Tensor, pocket: torch.Tensor, stream=None):
+    """scores [n_pockets, n] float32 -> best [n] (lowest per column), pocket [n] (its row, ties low)."""
+    _check(load().dock_merge_pockets(_ptr(scores), scores.shape[0], scores.shape[1], _ptr(best), _ptr(pocket),
+                                     _stream(stream)), "dock_merge_pockets")
 
 
 # ------------------------------------------------------------------------------------------------

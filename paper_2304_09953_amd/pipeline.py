@@ -161,6 +161,15 @@ def topk(scores: torch.Tensor, k: int, ids: torch.Tensor | None = None, stream=N
     return out_s, out_i
 
 
+def merge_pockets(scores: torch.Tensor, stream=None):
+    """Each ligand's best over pockets: scores [n_pockets, n] -> (best [n], pocket index [n])."""
+    scores = scores.contiguous()
+    best = torch.empty(scores.shape[1], dtype=torch.float32, device=scores.device)
+    pocket = torch.empty(scores.shape[1], dtype=torch.int32, device=scores.device)
+    dock.merge_pockets(scores, best, pocket, stream)
+    return best, pocket
+
+
 def score_poses(pocket: DevicePocket, lib: DeviceLibrary, search: DeviceSearch, lig, start, steps, stream=None):
     dev = pocket.grids.device
     lig = _dev(lig, dev, torch.int32)

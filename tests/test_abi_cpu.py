@@ -147,6 +147,9 @@ def test_size_queries_and_argument_errors():
     all_of_many = dock.SearchDesc(4096, fake, 4, fake, 64, 2.5, 10.0, 0, 0, 16384, 1)  # nothing to select
     assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(all_of_many), None, None,
                            None, None, None, None, None, ctypes.byref(sz), None) == 0
+    assert lib.dock_merge_pockets(fake, 0, 10, fake, fake, None) == -1
+    assert lib.dock_merge_pockets(fake, 2, 0, fake, fake, None) == -1
+    assert lib.dock_merge_pockets(None, 2, 10, fake, fake, None) == -1
     assert lib.dock_topk(None, None, 100, 10, None, None, None, ctypes.byref(sz), None) == 0
     assert lib.dock_topk(None, None, 100, 101, None, None, None, ctypes.byref(sz), None) == -1
     assert lib.dock_topk(None, None, 0, 1, None, None, None, ctypes.byref(sz), None) == -1

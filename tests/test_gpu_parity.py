@@ -370,6 +370,22 @@ def test_topk_vs_oracle(P, n, k, with_ids):
     assert np.array_equal(got_s.cpu().numpy(), np.where(np.isnan(ref_s), np.inf, ref_s).astype(np.float32))
 
 
+@pytest.mark.parametrize("n_pockets,n", [(1, 5), (4, 70001)])
+def test_merge_pockets_vs_definition(P, n_pockets, n):
+    rng = np.random.default_rng(n)
+    s = rng.integers(-20, 20, (n_pockets, n)).astype(np.float32) / 2  # many exact ties across pockets
+    s[rng.random((n_pockets, n)) < 0.05] = np.inf
+    s[rng.random((n_pockets, n)) < 0.02] = np.nan
+    s[:, :3] = np.inf  # ligands docked nowhere
+    say(f"merge {n_pockets} pockets x {n} ligands")
+    best, pocket = P.merge_pockets(torch.from_numpy(s).cuda())
+    t = np.where(np.isnan(s), np.inf, s)
+    ref_p = np.argmin(t, axis=0)  # the first row among equal minima
+    ref_b = t[ref_p, np.arange(n)]
+    ref_p = np.where(np.isinf(ref_b), -1, ref_p)
+    assert np.array_equal(best.cpu().numpy(), ref_b) and np.array_equal(pocket.cpu().numpy(), ref_p)
+
+
 # ------------------------------------------------------------------------------------------------
 # Full-size configuration 2 (96^3 x 16 grid, 256 x 32 starts, S = 256) on a stratified sample
 # ------------------------------------------------------------------------------------------------
