@@ -69,6 +69,8 @@ def _load():
         _lib = ctypes.CDLL(LIB_PATH)
         _lib.or_pair_energy.restype = ctypes.c_double
         _lib.or_pair_energy.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Potential)]
+        _lib.or_rescore_pair.restype = ctypes.c_double
+        _lib.or_rescore_pair.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Potential)]
     return _lib
 
 
@@ -323,6 +325,44 @@ def exhaustive(pocket, G, ligs, srch, l: int, periodic: bool = False):
 # ------------------------------------------------------------------------------------------------
 # Ranking and counting
 # ------------------------------------------------------------------------------------------------
+
+def _prot(pocket):
+    xyz = np.ascontiguousarray(pocket.prot_xyz, dtype=np.float32)
+    t = np.ascontiguousarray(pocket.prot_type, dtype=np.int32)
+    return xyz, t
+
+
+def filter_rescore(pocket, ligs, srch, l: int, start, steps, rmsd_min: float) -> dict:
+    """Pose filtering and rescoring of ligand l's poses (start[i], steps[i]) given in docking order."""
+    lib, s, pot = library(ligs), search(srch), potential(pocket)
+    xyz, t = _prot(pocket)
+    start = np.ascontiguousarray(start, dtype=np.int32)
+    n = len(start)
+    st = np.zeros((n, MAX_TORS), np.int32)
+    st[:, :np.shape(steps)[1]] = steps
+    kept = np.zeros(n, np.int32)
+    rescore = np.zeros(n, np.float64)
+    nearest = np.zeros(n, np.float64)
+    _load().or_filter_rescore(pot.ref, _p(xyz, _F32), _p(t, _I32), ctypes.c_int32(len(t)), lib.ref, s.ref,
+                              ctypes.c_int64(l), ctypes.c_int32(n), _p(start, _I32), _p(st, _I32),
+                              ctypes.c_double(rmsd_min), _p(kept, _I32), _p(rescore, _F64), _p(nearest, _F64))
+    return {"kept": kept.astype(bool), "rescore": rescore, "nearest": nearest}
+
+
+def rescore_conformer(pocket, ligs, srch, l: int, X) -> float:
+    lib, s, pot = library(ligs), search(srch), potential(pocket)
+    xyz, t = _prot(pocket)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    out = ctypes.c_double()
+    _load().or_rescore_conformer(pot.ref, _p(xyz, _F32), _p(t, _I32), ctypes.c_int32(len(t)), lib.ref, s.ref,
+                                 ctypes.c_int64(l), _p(X, _F64), ctypes.byref(out))
+    return out.value
+
+
+def rescore_pair(pocket, r: float, a: int, b: int) -> float:
+    pot = potential(pocket)
+    return _load().or_rescore_pair(float(r), int(a), int(b), ctypes.pointer(pot.struct))
+
 
 def set_threads(n: int) -> None:
     """OpenMP threads of the batch entry points (dock, score_poses, ...)."""

@@ -790,6 +790,108 @@ int or_pose_coords(const or_library *lib, const or_search *s, int64_t l, int32_t
     return 0;
 }
 
+/* ------------------------------------------------------------------------------------------ */
+/* Pose filtering and rescoring                                                                */
+/* ------------------------------------------------------------------------------------------ */
+
+/*
+ * Rescoring pair energy: the same 6-12 well as the grid potential, and Coulomb with the
+ * distance-dependent dielectric 4 r in place of the constant 4 (coulomb_k already holds the
+ * factor 1/4): coulomb_k q_a q_b / r'^2; r floored at r_min.
+ */
+double or_rescore_pair(double r, int a, int b, const or_potential *pot)
+{
+    double rt = r > pot->r_min ? r : pot->r_min;
+    double r0 = pot->R[a] + pot->R[b];
+    double eps = sqrt(pot->eps[a] * pot->eps[b]);
+    double s6 = pow(r0 / rt, 6.0);
+    return eps * (s6 * s6 - 2.0 * s6) + pot->coulomb_k * pot->q[a] * pot->q[b] / (rt * rt);
+}
+
+/*
+ * Rescoring of conformer X: for every ligand atom the sum of or_rescore_pair over the protein
+ * atoms at the atom's own position (no grid, no interpolation), capped at pot->cap, plus the
+ * intra-ligand clash term of the docking score.
+ */
+double or_rescore(const or_lig *L, const double X[][3], const or_potential *pot, const float *prot_xyz,
+                  const int32_t *prot_type, int32_t n_prot, const or_search *s)
+{
+    double e = 0.0;
+    for (int i = 0; i < L->n; ++i) {
+        double sum = 0.0;
+        for (int32_t p = 0; p < n_prot; ++p) {
+            double dx = X[i][0] - (double)prot_xyz[3 * p], dy = X[i][1] - (double)prot_xyz[3 * p + 1];
+            double dz = X[i][2] - (double)prot_xyz[3 * p + 2];
+            sum += or_rescore_pair(sqrt(dx * dx + dy * dy + dz * dz), L->type[i], prot_type[p], pot);
+        }
+        e += sum < pot->cap ? sum : pot->cap;
+    }
+    for (int q = 0; q < L->n_pairs; ++q) {
+        const double *a = X[L->pair_i[q]], *b = X[L->pair_j[q]];
+        double d = sqrt((a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) + (a[2] - b[2]) * (a[2] - b[2]));
+        if (d < s->clash_cut) e += s->clash_w * (s->clash_cut - d) * (s->clash_cut - d);
+    }
+    return e;
+}
+
+/* Root mean square deviation of two conformers of one ligand, atom by atom, no superposition. */
+double or_rmsd(int n, const double X[][3], const double Y[][3])
+{
+    double s = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) s += (X[i][d] - Y[i][d]) * (X[i][d] - Y[i][d]);
+    return sqrt(s / n);
+}
+
+/*
+ * Filters and rescores poses of ligand l given in docking order (start[i], steps[i][16]): a pose
+ * is kept unless an earlier kept pose lies within rmsd_min of it; kept poses get or_rescore,
+ * dropped ones NaN.  nearest[i] is the RMSD to the closest earlier kept pose (+inf if none).
+ * Poses with start < 0 are absent (dropped, NaN, +inf).
+ */
+int or_filter_rescore(const or_potential *pot, const float *prot_xyz, const int32_t *prot_type, int32_t n_prot,
+                      const or_library *lib, const or_search *s, int64_t l, int32_t n_poses, const int32_t *start,
+                      const int32_t *steps, double rmsd_min, int32_t *kept, double *rescore, double *nearest)
+{
+    or_lig *L = (or_lig *)malloc(sizeof(or_lig));
+    or_ligand(lib, l, L);
+    double(*P)[OR_MAX_ATOMS][3] = malloc(sizeof(double) * OR_MAX_ATOMS * 3 * (size_t)(n_poses > 0 ? n_poses : 1));
+    double Y[OR_MAX_ATOMS][3];
+    for (int32_t i = 0; i < n_poses; ++i) {
+        kept[i] = 0;
+        rescore[i] = NAN;
+        nearest[i] = INFINITY;
+        if (L->status != OR_LIG_OK || start[i] < 0) continue;
+        or_place(L, s, start[i], P[i]);
+        for (int k = 0; k < L->B; ++k) {
+            or_turn(L, s, k, steps[i * OR_MAX_TORS + k], (const double(*)[3])P[i], Y);
+            memcpy(P[i], Y, sizeof(double) * 3 * L->n);
+        }
+        for (int32_t j = 0; j < i; ++j) {
+            if (!kept[j]) continue;
+            double r = or_rmsd(L->n, (const double(*)[3])P[i], (const double(*)[3])P[j]);
+            if (r < nearest[i]) nearest[i] = r;
+        }
+        kept[i] = !(nearest[i] < rmsd_min);
+        if (kept[i]) rescore[i] = or_rescore(L, (const double(*)[3])P[i], pot, prot_xyz, prot_type, n_prot, s);
+    }
+    free(P);
+    free(L);
+    return 0;
+}
+
+/* Rescoring of explicit conformers X [n][3] of ligand l (any coordinates; pins the definition). */
+int or_rescore_conformer(const or_potential *pot, const float *prot_xyz, const int32_t *prot_type, int32_t n_prot,
+                         const or_library *lib, const or_search *s, int64_t l, const double *X, double *out)
+{
+    or_lig *L = (or_lig *)malloc(sizeof(or_lig));
+    or_ligand(lib, l, L);
+    *out = L->status == OR_LIG_OK ? or_rescore(L, (const double(*)[3])X, pot, prot_xyz, prot_type, n_prot, s)
+                                  : INFINITY;
+    free(L);
+    return 0;
+}
+
 void or_quat_matrix_c(const double *q, double *Rm) { or_quat_matrix(q, Rm); }
 void or_rodrigues_c(const double *u, double th, const double *v, double *out) { or_rodrigues(u, th, v, out); }
 
