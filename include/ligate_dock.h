@@ -178,6 +178,37 @@ int dock_screen(const dock_grid_desc *g, const float *d_grids, const void *d_pac
                 void *d_ws, size_t *ws_bytes, void *stream);
 
 /*
+ * Pose filtering and rescoring after dock_screen.  For every packed ligand: the
+ * n_keep searched starts with the lowest final scores in d_start_scores
+ * (dock_screen's per-start output, [n_lig][n_quat*n_trans]; ties to the lower
+ * start; +inf entries are not taken), in that order, each rerun with the
+ * screen's own code to recover its pose (its final equals the d_start_scores
+ * entry bit for bit).  Walking them in that order, a pose is dropped when an
+ * earlier kept pose lies within rmsd_min Angstrom of it (atom-by-atom RMSD, no
+ * superposition); every kept pose is rescored at its atoms' own positions, in
+ * FP64: per ligand atom min(cap, sum over the protein atoms of
+ * sqrt(eps_a eps_b)[(r0/r')^12 - 2(r0/r')^6] + coulomb_k q_a q_b / r'^2)
+ * (the grid potential with the distance-dependent dielectric 4r in place of 4,
+ * no grid, no interpolation), plus the intra-ligand clash term.
+ * g, d_grids, d_pack, n_lig, n_atoms_total, s: as for dock_screen (the same
+ * search; n_quat*n_trans <= DOCK_MAX_TOP_STARTS).  Protein and potential: as
+ * for dock_build_grids.  1 <= n_keep <= 16; rmsd_min >= 0 (Angstrom).
+ * Outputs [n_lig][n_keep]: d_pose_start (-1 where there is no pose),
+ * d_pose_steps [..][16] (total turns), d_pose_score (docking score, NaN where
+ * no pose), d_pose_rescore (NaN where dropped or absent); [n_lig]:
+ * d_best_rescore (lowest rescore, +inf if none), d_best_pose (its slot, ties
+ * to the earlier slot; -1 if none).  Optional d_pose_xyz
+ * [n_lig][n_keep][128][3] FP64 (the coordinates each kept pose was rescored
+ * at; NULL to skip).  No workspace.
+ */
+int dock_rescore(const dock_grid_desc *g, const float *d_grids, const void *d_pack, int32_t n_lig,
+                 int64_t n_atoms_total, const dock_search *s, const float *d_start_scores, const float *d_prot_xyz,
+                 const int32_t *d_prot_type, int32_t n_prot, const dock_type_param *h_params,
+                 const dock_potential *pot, int32_t n_keep, float rmsd_min, int32_t *d_pose_start,
+                 uint16_t *d_pose_steps, float *d_pose_score, float *d_pose_rescore, float *d_best_rescore,
+                 int32_t *d_best_pose, double *d_pose_xyz, void *stream);
+
+/*
  * Ranks scores: the k lowest, ties to the lower id, NaN ranked as +inf;
  * results in ascending order.  d_ids [n] (>= 0) or NULL for ids 0..n-1.
  * 1 <= k <= n < 2^31.  Workspace: query with d_ws == NULL.

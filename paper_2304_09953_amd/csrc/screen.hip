@@ -736,6 +736,60 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
     return base + inc - v;
 }
 
+struct SelectScratch {
+    uint32_t hist[256];
+    uint32_t scan[2][kTopBlock / kWave];
+    uint32_t prefix, need;
+};
+
+// The K lowest of the n keys key[0..n) (in LDS), ties to the lower index, found by a radix select
+// eight bits at a time from the top; their indices are written to out[0..K) in increasing order.
+// 1 <= K <= n.  All kTopBlock threads of the block must call it.
+__device__ void block_select_lowest(const uint32_t *key, int n, int K, uint32_t *out, SelectScratch &sc) {
+    const int tid = threadIdx.x;
+    // the K-th smallest key; `need` of the keys equal to it belong to the K lowest
+    uint32_t prefix = 0, mask = 0, need = (uint32_t)K;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        sc.hist[tid] = 0u;
+        __syncthreads();
+        for (int p = tid; p < n; p += kTopBlock) {
+            const uint32_t k = key[p];
+            if ((k & mask) == prefix) atomicAdd(&sc.hist[(k >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t acc = 0, d = 0;
+            for (; d < 255u; ++d) {
+                if (acc + sc.hist[d] >= need) break;
+                acc += sc.hist[d];
+            }
+            sc.need = need - acc;
+            sc.prefix = prefix | (d << shift);
+        }
+        __syncthreads();
+        need = sc.need;
+        prefix = sc.prefix;
+        mask |= 255u << shift;
+        __syncthreads();
+    }
+    // order-preserving compaction: thread t owns the indices [t chunk, (t + 1) chunk)
+    const int chunk = (n + kTopBlock - 1) / kTopBlock;
+    const int b0 = min(tid * chunk, n), b1 = min(b0 + chunk, n);
+    uint32_t n_less = 0, n_eq = 0;
+    for (int p = b0; p < b1; ++p) {
+        n_less += key[p] < prefix;
+        n_eq += key[p] == prefix;
+    }
+    uint32_t less = block_exclusive_scan(n_less, sc.scan[0]);
+    uint32_t eq = block_exclusive_scan(n_eq, sc.scan[1]);
+    for (int p = b0; p < b1; ++p) {
+        const uint32_t k = key[p];
+        if (k < prefix || (k == prefix && eq < need)) out[less + min(eq, need)] = (uint32_t)p;
+        less += k < prefix;
+        eq += k == prefix;
+    }
+}
+
 // Search budget: the rigid score of every start of one ligand (the same arithmetic as the screen's
 // rigid placement), then the K lowest, ties to the lower start, by a radix select over the ordered
 // 32-bit scores (a start's index is its position).  Writes the chosen starts in increasing order to
@@ -746,9 +800,7 @@ __global__ __launch_bounds__(kTopBlock) void k_rigid_top(ScreenArgs A, uint32_t 
     extern __shared__ __align__(16) char smem[];
     LigLDS &L = *reinterpret_cast<LigLDS *>(smem);
     uint32_t *key = reinterpret_cast<uint32_t *>(smem + ((sizeof(LigLDS) + 15) & ~size_t(15)));  // [QT]
-    __shared__ uint32_t hist[256];
-    __shared__ uint32_t scan_s[2][kTopBlock / kWave];
-    __shared__ uint32_t prefix_s, need_s;
+    __shared__ SelectScratch sc;
     __shared__ float clash_s;
     const int lig = blockIdx.x, tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     const int QT = A.s.QT, K = A.s.top;
@@ -777,48 +829,7 @@ __global__ __launch_bounds__(kTopBlock) void k_rigid_top(ScreenArgs A, uint32_t 
         if (lane == 0) key[p] = float_to_ordered(E);
     }
     __syncthreads();
-    // the K-th smallest key, eight bits at a time from the top; `need` of the keys equal to it
-    // belong to the K lowest
-    uint32_t prefix = 0, mask = 0, need = (uint32_t)K;
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        hist[tid] = 0u;
-        __syncthreads();
-        for (int p = tid; p < QT; p += kTopBlock) {
-            const uint32_t k = key[p];
-            if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t acc = 0, d = 0;
-            for (; d < 255u; ++d) {
-                if (acc + hist[d] >= need) break;
-                acc += hist[d];
-            }
-            need_s = need - acc;
-            prefix_s = prefix | (d << shift);
-        }
-        __syncthreads();
-        need = need_s;
-        prefix = prefix_s;
-        mask |= 255u << shift;
-        __syncthreads();
-    }
-    // order-preserving compaction: thread t owns the starts [t chunk, (t + 1) chunk)
-    const int chunk = (QT + kTopBlock - 1) / kTopBlock;
-    const int b0 = min(tid * chunk, QT), b1 = min(b0 + chunk, QT);
-    uint32_t n_less = 0, n_eq = 0;
-    for (int p = b0; p < b1; ++p) {
-        n_less += key[p] < prefix;
-        n_eq += key[p] == prefix;
-    }
-    uint32_t less = block_exclusive_scan(n_less, scan_s[0]);
-    uint32_t eq = block_exclusive_scan(n_eq, scan_s[1]);
-    for (int p = b0; p < b1; ++p) {
-        const uint32_t k = key[p];
-        if (k < prefix || (k == prefix && eq < need)) sel[(size_t)lig * K + less + min(eq, need)] = (uint32_t)p;
-        less += k < prefix;
-        eq += k == prefix;
-    }
+    block_select_lowest(key, QT, K, sel + (size_t)lig * K, sc);
 }
 
 template <int APL, int BOUNDARY, int LAYOUT>
@@ -950,6 +961,253 @@ __global__ __launch_bounds__(64) void k_score_poses(GridC g, SearchC s, PackView
 }
 
 // ---------------------------------------------------------------------------------------------
+// Pose filtering and rescoring
+// ---------------------------------------------------------------------------------------------
+
+constexpr int kMaxKeep = 16;
+
+// The n_keep searched starts with the lowest final scores (ties to the lower start; +inf entries,
+// i.e. starts not searched, are never taken), in that order; -1 where there are fewer, and for a
+// ligand whose status is not OK (the screen leaves its entries unwritten).
+__global__ __launch_bounds__(kTopBlock) void k_pick_poses(const LigDesc *desc, const float *start_scores, int QT,
+                                                          int n_keep, int32_t *pose_start) {
+    __shared__ uint32_t key[DOCK_MAX_TOP_STARTS];
+    __shared__ uint32_t sel[kMaxKeep];
+    __shared__ SelectScratch sc;
+    const int lig = blockIdx.x, tid = threadIdx.x;
+    if (desc[lig].status != DOCK_LIG_OK) {  // block-uniform
+        for (int i = tid; i < n_keep; i += kTopBlock) pose_start[(size_t)lig * n_keep + i] = -1;
+        return;
+    }
+    for (int p = tid; p < QT; p += kTopBlock) key[p] = float_to_ordered(start_scores[(size_t)lig * QT + p]);
+    __syncthreads();
+    const int K = min(n_keep, QT);
+    block_select_lowest(key, QT, K, sel, sc);
+    __syncthreads();
+    if (tid == 0) {
+        // order by (score, start): insertion sort of at most 16
+        for (int i = 1; i < K; ++i) {
+            const uint32_t v = sel[i];
+            int j = i - 1;
+            while (j >= 0 && key[sel[j]] > key[v]) {
+                sel[j + 1] = sel[j];
+                --j;
+            }
+            sel[j + 1] = v;
+        }
+        const uint32_t inf_key = float_to_ordered(INFINITY);
+        for (int i = 0; i < n_keep; ++i)
+            pose_start[(size_t)lig * n_keep + i] = i < K && key[sel[i]] < inf_key ? (int32_t)sel[i] : -1;
+    }
+}
+
+struct PoseArgs {
+    ScreenArgs A;  // grid, search, pack
+    const int32_t *pose_start;
+    uint16_t *pose_steps;
+    float *pose_score;
+    int n_keep;
+};
+
+// One wavefront per (ligand, kept slot): reruns the start with the screen's code to recover its
+// total turns; the final equals the screen's per-start score bit for bit.
+template <int APL, int BOUNDARY, int LAYOUT>
+__global__ __launch_bounds__(64) void k_pose_replay(PoseArgs R) {
+    extern __shared__ __align__(16) char smem[];
+    LigLDS &L = *reinterpret_cast<LigLDS *>(smem);
+    WaveLDS &W = *reinterpret_cast<WaveLDS *>(smem + ((sizeof(LigLDS) + 15) & ~size_t(15)));
+    const int lig = blockIdx.x / R.n_keep, slot = blockIdx.x - lig * R.n_keep, lane = lane_id();
+    const ScreenArgs &A = R.A;
+    const int p = R.pose_start[(size_t)lig * R.n_keep + slot];
+    uint16_t *steps = R.pose_steps + ((size_t)lig * R.n_keep + slot) * DOCK_MAX_TORSIONS;
+    if (p < 0) {
+        if (lane < DOCK_MAX_TORSIONS) steps[lane] = 0;
+        if (lane == 0) R.pose_score[(size_t)lig * R.n_keep + slot] = NAN;
+        return;
+    }
+    float cs[APL], sn[APL];
+    angle_table<APL>(A.s.S, cs, sn);
+    const rsrc_t rs = grid_rsrc(A.g);
+    load_ligand(L, A.pk, lig, A.g, lane, kWave);
+    __syncthreads();
+    int step = 0;
+    const float E = run_start<APL, BOUNDARY, LAYOUT>(A.g, rs, A.s, L, W, p, rigid_clash(L, A.s), cs, sn, step);
+    if (lane < DOCK_MAX_TORSIONS) steps[lane] = (uint16_t)(lane < L.B ? step : 0);
+    if (lane == 0) R.pose_score[(size_t)lig * R.n_keep + slot] = E;
+}
+
+struct RescoreArgs {
+    GridC g;
+    SearchC s;
+    PackView pk;
+    const float *prot_xyz;
+    const int32_t *prot_type;
+    int n_prot;
+    // per type: radius, square root of the well depth, charge; the pair terms are R_a + R_b,
+    // sqrt(eps_a) sqrt(eps_b) and coulomb_k q_a q_b
+    double R[DOCK_MAX_TYPES], se[DOCK_MAX_TYPES], q[DOCK_MAX_TYPES];
+    double coulomb_k, cap, r_min, h, ox, oy, oz, rmsd2_min, clash_cut, clash_w;
+    int n_keep;
+    const int32_t *pose_start;
+    const uint16_t *pose_steps;
+    float *pose_rescore, *best_rescore;
+    int32_t *best_pose;
+    double *pose_xyz;  // optional [n_lig][n_keep][128][3]
+};
+
+constexpr int kProtTile = 256;
+
+// One wavefront per ligand: rebuilds its kept-slot poses in docking order (the k_score_poses code),
+// drops a pose within rmsd_min of an earlier kept one, and rescores the rest in FP64 at the atoms'
+// own positions (protein atoms staged in LDS), then picks the best.
+__global__ __launch_bounds__(64) void k_filter_rescore(RescoreArgs R) {
+    __shared__ LigLDS L;
+    __shared__ float4 kept_xyz[kMaxKeep][DOCK_MAX_ATOMS];  // grid units
+    __shared__ float4 prot[kProtTile];
+    __shared__ double prot_R[kProtTile], prot_se[kProtTile], prot_q[kProtTile];
+    const int lig = blockIdx.x, lane = lane_id();
+    load_ligand(L, R.pk, lig, R.g, lane, kWave);
+    __syncthreads();
+    float best = INFINITY;
+    int best_i = -1, n_kept = 0;
+    for (int i = 0; i < R.n_keep; ++i) {
+        const size_t slot = (size_t)lig * R.n_keep + i;
+        const int p = R.pose_start[slot];
+        if (p < 0 || L.status != DOCK_LIG_OK) {
+            if (lane == 0) R.pose_rescore[slot] = NAN;
+            continue;
+        }
+        // the pose, as k_score_poses builds it (grid units)
+        const int n = L.n;
+        float cx[2], cy[2], cz[2];
+        place(R.g, R.s, L, p, cx, cy, cz);
+        for (int k = 0; k < L.B; ++k) {
+            const TorRec tr = L.tor[k];
+            const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
+            float xax, xay, xaz, ux, uy, uz;
+            axis(tr, cx, cy, cz, xax, xay, xaz, ux, uy, uz);
+            float sb, cb;
+            sincospif(2.0f * (float)R.pose_steps[slot * DOCK_MAX_TORSIONS + k] / (float)R.s.S, &sb, &cb);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int a = lane + kWave * h;
+                if (a < n && mask_has(mask, a)) {
+                    float px, py, pz, ax, ay, az, bx, by, bz;
+                    circle(ux, uy, uz, xax, xay, xaz, cx[h], cy[h], cz[h], px, py, pz, ax, ay, az, bx, by, bz);
+                    cx[h] = fmaf(ax, cb, fmaf(bx, sb, px));
+                    cy[h] = fmaf(ay, cb, fmaf(by, sb, py));
+                    cz[h] = fmaf(az, cb, fmaf(bz, sb, pz));
+                }
+            }
+        }
+        // world coordinates in FP64: x = origin + h u
+        double wx[2], wy[2], wz[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            wx[h] = fma((double)cx[h], R.h, R.ox);
+            wy[h] = fma((double)cy[h], R.h, R.oy);
+            wz[h] = fma((double)cz[h], R.h, R.oz);
+        }
+        // the RMSD to every earlier kept pose (squared, Angstrom^2, FP64 sums)
+        bool keep = true;
+        for (int j = 0; j < n_kept; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int a = lane + kWave * h;
+                if (a < n) {
+                    const float4 y = kept_xyz[j][a];
+                    const double dx = (double)(cx[h] - y.x), dy = (double)(cy[h] - y.y), dz = (double)(cz[h] - y.z);
+                    acc += dx * dx + dy * dy + dz * dz;
+                }
+            }
+            const double msd = wave_sum_d(acc) * R.h * R.h / n;
+            if (msd < R.rmsd2_min) keep = false;
+        }
+        if (!keep) {
+            if (lane == 0) R.pose_rescore[slot] = NAN;
+            continue;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int a = lane + kWave * h;
+            if (a < n) kept_xyz[n_kept][a] = make_float4(cx[h], cy[h], cz[h], 0.0f);
+        }
+        ++n_kept;
+        if (R.pose_xyz) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int a = lane + kWave * h;
+                if (a < n) {
+                    double *o = R.pose_xyz + (slot * DOCK_MAX_ATOMS + a) * 3;
+                    o[0] = wx[h];
+                    o[1] = wy[h];
+                    o[2] = wz[h];
+                }
+            }
+        }
+        // per atom: capped FP64 sum over the protein atoms
+        double sum[2] = {0.0, 0.0};
+        for (int base = 0; base < R.n_prot; base += kProtTile) {
+            __syncthreads();
+            for (int q = lane; q < kProtTile && base + q < R.n_prot; q += kWave) {
+                const int j = base + q, tb = min(max(R.prot_type[j], 0), DOCK_MAX_TYPES - 1);
+                prot[q] = make_float4(R.prot_xyz[3 * j], R.prot_xyz[3 * j + 1], R.prot_xyz[3 * j + 2], 0.0f);
+                prot_R[q] = R.R[tb];
+                prot_se[q] = R.se[tb];
+                prot_q[q] = R.q[tb];
+            }
+            __syncthreads();
+            const int cnt = min(kProtTile, R.n_prot - base);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int a = lane + kWave * h;
+                if (a >= n) continue;
+                const int ta = L.tof[a] / R.g.type_bytes;
+                const double Ra = R.R[ta], sea = R.se[ta], kqa = R.coulomb_k * R.q[ta];
+                for (int q = 0; q < cnt; ++q) {
+                    const float4 pa = prot[q];
+                    const double dx = wx[h] - (double)pa.x, dy = wy[h] - (double)pa.y, dz = wz[h] - (double)pa.z;
+                    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                    const double rt = r > R.r_min ? r : R.r_min;
+                    const double sr = (Ra + prot_R[q]) / rt, s2 = sr * sr, s6 = s2 * s2 * s2;
+                    sum[h] += sea * prot_se[q] * (s6 * s6 - 2.0 * s6) + kqa * prot_q[q] / (rt * rt);
+                }
+            }
+        }
+        double e = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (lane + kWave * h < n) e += sum[h] < R.cap ? sum[h] : R.cap;
+        // the intra-ligand clash term, FP64 from the same coordinates
+        for (int a = 0; a < n; ++a) {
+            const double xa = __shfl(a < kWave ? wx[0] : wx[1], a & 63), ya = __shfl(a < kWave ? wy[0] : wy[1], a & 63),
+                         za = __shfl(a < kWave ? wz[0] : wz[1], a & 63);
+            const uint4 ex = L.excl[a];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int b = lane + kWave * h;
+                if (b > a && b < n && !mask_has(ex, b)) {
+                    const double dx = wx[h] - xa, dy = wy[h] - ya, dz = wz[h] - za;
+                    const double d = sqrt(dx * dx + dy * dy + dz * dz);
+                    if (d < R.clash_cut) e += R.clash_w * (R.clash_cut - d) * (R.clash_cut - d);
+                }
+            }
+        }
+        const double tot = wave_sum_d(e);
+        if (lane == 0) R.pose_rescore[slot] = (float)tot;
+        if ((float)tot < best) {
+            best = (float)tot;
+            best_i = i;
+        }
+    }
+    if (lane == 0) {
+        R.best_rescore[lig] = best;
+        R.best_pose[lig] = best_i;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------------------------
 
@@ -1068,6 +1326,21 @@ static int dispatch_boundary(int boundary, int S, const ScreenArgs &A, float *bs
     return dispatch_apl<DOCK_BOUNDARY_CLAMP, LAYOUT>(S, A, bs, bp, bst, st);
 }
 
+template <int APL, int BOUNDARY, int LAYOUT>
+static void launch_pose_replay(const PoseArgs &R, int n_lig, hipStream_t st) {
+    hipLaunchKernelGGL((k_pose_replay<APL, BOUNDARY, LAYOUT>), dim3((unsigned)(n_lig * R.n_keep)), dim3(kWave),
+                       screen_lds(1), st, R);
+}
+
+template <int BOUNDARY, int LAYOUT>
+static void replay_apl(int S, const PoseArgs &R, int n_lig, hipStream_t st) {
+    if (S <= 64) return launch_pose_replay<1, BOUNDARY, LAYOUT>(R, n_lig, st);
+    if (S <= 128) return launch_pose_replay<2, BOUNDARY, LAYOUT>(R, n_lig, st);
+    if (S <= 256) return launch_pose_replay<4, BOUNDARY, LAYOUT>(R, n_lig, st);
+    if (S <= 512) return launch_pose_replay<8, BOUNDARY, LAYOUT>(R, n_lig, st);
+    return launch_pose_replay<16, BOUNDARY, LAYOUT>(R, n_lig, st);
+}
+
 static int default_cu_count() {
     int dev = 0, cu = 0;
     (void)hipGetDevice(&dev);
@@ -1180,4 +1453,76 @@ extern "C" int dock_score_poses(const dock_grid_desc *gd, const float *d_grids, 
         hipLaunchKernelGGL((k_score_poses<DOCK_BOUNDARY_CLAMP, DOCK_LAYOUT_LINEAR>), grid, block, 0, st, g, s, pk,
                            n_lig, d_lig, d_start, d_steps, n_poses, d_scores);
     return check_launch("dock_score_poses");
+}
+
+extern "C" int dock_rescore(const dock_grid_desc *gd, const float *d_grids, const void *d_pack, int32_t n_lig,
+                            int64_t n_atoms_total, const dock_search *sd, const float *d_start_scores,
+                            const float *d_prot_xyz, const int32_t *d_prot_type, int32_t n_prot,
+                            const dock_type_param *h_params, const dock_potential *pot, int32_t n_keep,
+                            float rmsd_min, int32_t *d_pose_start, uint16_t *d_pose_steps, float *d_pose_score,
+                            float *d_pose_rescore, float *d_best_rescore, int32_t *d_best_pose, double *d_pose_xyz,
+                            void *stream) {
+    int rc = grid_desc_check(gd);
+    if (rc) return rc;
+    rc = check_search(sd);
+    if (rc) return rc;
+    LIGATE_REQUIRE(n_lig >= 1 && n_atoms_total >= 0 && n_atoms_total < (1ll << 31), DOCK_ERR_INVALID_ARG,
+                   "bad library size");
+    LIGATE_REQUIRE(n_keep >= 1 && n_keep <= kMaxKeep, DOCK_ERR_INVALID_ARG, "n_keep must be in [1, %d]", kMaxKeep);
+    LIGATE_REQUIRE(rmsd_min >= 0.0f, DOCK_ERR_INVALID_ARG, "rmsd_min must be >= 0");
+    LIGATE_REQUIRE((int64_t)sd->n_quat * sd->n_trans <= DOCK_MAX_TOP_STARTS, DOCK_ERR_LIMIT,
+                   "picking poses needs n_quat * n_trans <= %d", DOCK_MAX_TOP_STARTS);
+    LIGATE_REQUIRE(n_prot >= 0 && (n_prot == 0 || (d_prot_xyz && d_prot_type)), DOCK_ERR_INVALID_ARG,
+                   "protein arrays are NULL");
+    LIGATE_REQUIRE(h_params && pot && pot->r_min > 0.0, DOCK_ERR_INVALID_ARG, "bad potential");
+    LIGATE_REQUIRE(d_grids && d_pack && d_start_scores && d_pose_start && d_pose_steps && d_pose_score &&
+                       d_pose_rescore && d_best_rescore && d_best_pose,
+                   DOCK_ERR_INVALID_ARG, "NULL array");
+    hipStream_t st = (hipStream_t)stream;
+    ScreenArgs A{};
+    A.g = make_grid(gd, d_grids);
+    A.s = make_search(sd, gd->spacing);
+    A.pk = PackView::of(d_pack, n_lig, n_atoms_total);
+    A.n_lig = n_lig;
+    hipLaunchKernelGGL(k_pick_poses, dim3((unsigned)n_lig), dim3(kTopBlock), 0, st, A.pk.desc, d_start_scores,
+                       A.s.QT, n_keep, d_pose_start);
+    PoseArgs R{A, d_pose_start, d_pose_steps, d_pose_score, n_keep};
+    const bool per = gd->boundary == DOCK_BOUNDARY_PERIODIC, xy4 = gd->layout == DOCK_LAYOUT_XY4;
+    if (per && xy4) replay_apl<DOCK_BOUNDARY_PERIODIC, DOCK_LAYOUT_XY4>(A.s.S, R, n_lig, st);
+    else if (per) replay_apl<DOCK_BOUNDARY_PERIODIC, DOCK_LAYOUT_LINEAR>(A.s.S, R, n_lig, st);
+    else if (xy4) replay_apl<DOCK_BOUNDARY_CLAMP, DOCK_LAYOUT_XY4>(A.s.S, R, n_lig, st);
+    else replay_apl<DOCK_BOUNDARY_CLAMP, DOCK_LAYOUT_LINEAR>(A.s.S, R, n_lig, st);
+    RescoreArgs Q{};
+    Q.g = A.g;
+    Q.s = A.s;
+    Q.pk = A.pk;
+    Q.prot_xyz = d_prot_xyz;
+    Q.prot_type = d_prot_type;
+    Q.n_prot = n_prot;
+    for (int t = 0; t < DOCK_MAX_TYPES; ++t) {
+        const dock_type_param p = t < gd->n_types ? h_params[t] : dock_type_param{1.0, 0.0, 0.0};
+        LIGATE_REQUIRE(p.eps >= 0.0, DOCK_ERR_INVALID_ARG, "eps of type %d is negative", t);
+        Q.R[t] = p.R;
+        Q.se[t] = sqrt(p.eps);
+        Q.q[t] = p.q;
+    }
+    Q.coulomb_k = pot->coulomb_k;
+    Q.cap = pot->cap;
+    Q.r_min = pot->r_min;
+    Q.h = gd->spacing;
+    Q.ox = gd->origin[0];
+    Q.oy = gd->origin[1];
+    Q.oz = gd->origin[2];
+    Q.rmsd2_min = (double)rmsd_min * (double)rmsd_min;
+    Q.clash_cut = sd->clash_cut;
+    Q.clash_w = sd->clash_w;
+    Q.n_keep = n_keep;
+    Q.pose_start = d_pose_start;
+    Q.pose_steps = d_pose_steps;
+    Q.pose_rescore = d_pose_rescore;
+    Q.best_rescore = d_best_rescore;
+    Q.best_pose = d_best_pose;
+    Q.pose_xyz = d_pose_xyz;
+    hipLaunchKernelGGL(k_filter_rescore, dim3((unsigned)n_lig), dim3(kWave), 0, st, Q);
+    return check_launch("dock_rescore");
 }

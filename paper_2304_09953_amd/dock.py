@@ -28,7 +28,7 @@ LIG_STATUS = {0: "ok", 1: "n_atoms", 2: "type", 3: "n_bonds", 4: "bond_index", 5
               7: "terminal_rotatable", 8: "n_torsions"}
 
 EXPORTS = ("dock_grid_bytes", "dock_build_grids", "dock_pack_ligands", "dock_screen", "dock_topk",
-           "dock_merge_pockets", "dock_score_poses", "dock_error_string", "dock_last_error")
+           "dock_merge_pockets", "dock_score_poses", "dock_rescore", "dock_error_string", "dock_last_error")
 
 
 class GridDesc(ctypes.Structure):
@@ -74,6 +74,8 @@ def load() -> ctypes.CDLL:
         lib.dock_topk.argtypes = [vp, vp, i64, i32, vp, vp, vp, P(sz), vp]
         lib.dock_score_poses.argtypes = [P(GridDesc), vp, vp, i32, i64, P(SearchDesc), vp, vp, vp, i64, vp, vp]
         lib.dock_merge_pockets.argtypes = [vp, i32, i64, vp, vp, vp]
+        lib.dock_rescore.argtypes = [P(GridDesc), vp, vp, i32, i64, P(SearchDesc), vp, vp, vp, i32, P(TypeParam),
+                                     P(Potential), i32, ctypes.c_float, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.dock_error_string.restype = ctypes.c_char_p
         lib.dock_error_string.argtypes = [ctypes.c_int]
         lib.dock_last_error.restype = ctypes.c_char_p
@@ -138,6 +140,20 @@ def build_grids(desc: GridDesc, prot_xyz: torch.Tensor, prot_type: torch.Tensor,
     _check(load().dock_build_grids(ctypes.byref(desc), _ptr(prot_xyz), _ptr(prot_type), prot_type.numel(), params,
                                    ctypes.byref(pot), _ptr(out), _stream(stream)), "dock_build_grids")
     return out
+
+
+def rescore(desc: GridDesc, grids: torch.Tensor, pack: torch.Tensor, n_lig: int, n_atoms: int, search: SearchDesc,
+            start_scores: torch.Tensor, prot_xyz: torch.Tensor, prot_type: torch.Tensor, type_R, type_eps, type_q,
+            cap: float, r_min: float, coulomb_k: float, n_keep: int, rmsd_min: float, pose_start, pose_steps,
+            pose_score, pose_rescore, best_rescore, best_pose, pose_xyz=None, stream=None):
+    T = desc.n_types
+    params = (TypeParam * T)(*[TypeParam(float(type_R[t]), float(type_eps[t]), float(type_q[t])) for t in range(T)])
+    pot = Potential(float(cap), float(r_min), float(coulomb_k))
+    _check(load().dock_rescore(ctypes.byref(desc), _ptr(grids), _ptr(pack), n_lig, n_atoms, ctypes.byref(search),
+                               _ptr(start_scores), _ptr(prot_xyz), _ptr(prot_type), prot_type.numel(), params,
+                               ctypes.byref(pot), n_keep, float(rmsd_min), _ptr(pose_start), _ptr(pose_steps),
+                               _ptr(pose_score), _ptr(pose_rescore), _ptr(best_rescore), _ptr(best_pose),
+                               _ptr(pose_xyz), _stream(stream)), "dock_rescore")
 
 
 def pack_bytes(n_lig: int, n_atoms: int, n_types: int) -> int:

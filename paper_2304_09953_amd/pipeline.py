@@ -161,6 +161,37 @@ def topk(scores: torch.Tensor, k: int, ids: torch.Tensor | None = None, stream=N
     return out_s, out_i
 
 
+@dataclass
+class RescoreResult:
+    pose_start: torch.Tensor    # [n_lig, n_keep] int32 (-1: no pose)
+    pose_steps: torch.Tensor    # [n_lig, n_keep, 16] int16 (total turns)
+    pose_score: torch.Tensor    # [n_lig, n_keep] docking score
+    pose_rescore: torch.Tensor  # [n_lig, n_keep] (NaN: dropped or absent)
+    best_rescore: torch.Tensor  # [n_lig]
+    best_pose: torch.Tensor     # [n_lig] slot of the best kept pose (-1: none)
+    pose_xyz: torch.Tensor | None  # [n_lig, n_keep, 128, 3] float64 when asked for
+
+
+def rescore(pocket: DevicePocket, lib: DeviceLibrary, search: DeviceSearch, start_scores: torch.Tensor,
+            n_keep: int = 8, rmsd_min: float = 1.0, want_xyz: bool = False, stream=None) -> RescoreResult:
+    """Pose filtering and rescoring of the screen's per-start results (dock_rescore)."""
+    dev = pocket.grids.device
+    n = lib.n_lig
+    out = RescoreResult(torch.empty((n, n_keep), dtype=torch.int32, device=dev),
+                        torch.empty((n, n_keep, dock.MAX_TORSIONS), dtype=torch.int16, device=dev),
+                        torch.empty((n, n_keep), dtype=torch.float32, device=dev),
+                        torch.empty((n, n_keep), dtype=torch.float32, device=dev),
+                        torch.empty(n, dtype=torch.float32, device=dev),
+                        torch.empty(n, dtype=torch.int32, device=dev),
+                        torch.zeros((n, n_keep, 128, 3), dtype=torch.float64, device=dev) if want_xyz else None)
+    pk = pocket.pocket
+    dock.rescore(pocket.desc, pocket.grids, lib.pack, n, lib.n_atoms, search.desc, start_scores, pocket.prot_xyz,
+                 pocket.prot_type, pk.type_R, pk.type_eps, pk.type_q, pk.cap, pk.r_min, pk.coulomb_k, n_keep, rmsd_min,
+                 out.pose_start, out.pose_steps, out.pose_score, out.pose_rescore, out.best_rescore, out.best_pose,
+                 out.pose_xyz, stream)
+    return out
+
+
 def merge_pockets(scores: torch.Tensor, stream=None):
     """Each ligand's best over pockets: scores [n_pockets, n] -> (best [n], pocket index [n])."""
     scores = scores.contiguous()

@@ -1,0 +1,79 @@
+"""Pose filtering and rescoring on the GPU (dock_rescore) against the oracle."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2304_09953_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_09953_amd import pipeline as P
+    W = I.workload("pocket48-lib100")
+    pocket = W.pockets[0]
+    ligs = W.ligands().subset(np.arange(0, 100, 5))
+    return P, W, pocket, ligs, P.DevicePocket(pocket), P.DeviceLibrary(ligs)
+
+
+@pytest.mark.parametrize("n_keep,rmsd_min,top,passes", [(8, 1.0, 0, 1), (16, 2.5, 40, 2), (3, 0.0, 0, 1)])
+def test_rescore_matches_oracle(env, n_keep, rmsd_min, top, passes):
+    P, W, pocket, ligs, dp, lib = env
+    srch = dataclasses.replace(W.search, sweep_top=top, passes=passes)
+    ds = P.DeviceSearch(srch)
+    QT, n = srch.n_starts, ligs.n_lig
+    say(f"rescore: keep {n_keep}, rmsd_min {rmsd_min}, sweep_top {top}, passes {passes}")
+    scr = P.screen(dp, lib, ds, start_scores=True)
+    res = P.rescore(dp, lib, ds, scr.start_scores.view(n, QT), n_keep, rmsd_min, want_xyz=True)
+    torch.cuda.synchronize()
+    fin = scr.start_scores.view(n, QT).cpu().numpy()
+    start = res.pose_start.cpu().numpy()
+    steps = P.steps_numpy(res.pose_steps.view(-1)).reshape(n, n_keep, -1)
+    score = res.pose_score.cpu().numpy()
+    resc = res.pose_rescore.cpu().numpy().astype(np.float64)
+    xyz = res.pose_xyz.cpu().numpy()
+    best, best_pose = res.best_rescore.cpu().numpy(), res.best_pose.cpu().numpy()
+    flips = 0
+    for l in range(n):
+        # picks: the n_keep lowest finals of this screen (the same FP32 values), ties to the lower start
+        order = np.lexsort((np.arange(QT), fin[l]))[:n_keep]
+        order = order[np.isfinite(fin[l][order])]
+        want = np.full(n_keep, -1)
+        want[:len(order)] = order
+        assert np.array_equal(start[l], want), l
+        live = start[l] >= 0
+        assert np.array_equal(score[l][live], fin[l][start[l][live]])  # the replay reproduces the screen
+        orc = oracle.filter_rescore(pocket, ligs, srch, l, start[l], steps[l], rmsd_min)
+        kept = np.isfinite(resc[l])
+        na = ligs.n_atoms[l]
+        for i in np.flatnonzero(kept):
+            X = oracle.pose_coords(ligs, srch, l, int(start[l][i]), steps[l][i])
+            assert np.abs(xyz[l, i, :na] - X).max() < 1e-4  # the FP32 pose against the FP64 one
+            ref = oracle.rescore_conformer(pocket, ligs, srch, l, xyz[l, i, :na])
+            assert abs(resc[l][i] - ref) <= 1e-6 * max(1.0, abs(ref)), (l, i, resc[l][i], ref)
+        # filter decisions agree up to the first RMSD within 1e-4 of the threshold (FP32 poses)
+        for i in range(n_keep):
+            if kept[i] != orc["kept"][i]:
+                assert abs(orc["nearest"][i] - rmsd_min) < 1e-4, (l, i, orc["nearest"][i])
+                flips += 1
+                break
+        # best: the lowest kept rescore, ties to the earlier slot
+        if kept.any():
+            b = int(np.flatnonzero(kept)[np.argmin(resc[l][kept])])
+            assert best_pose[l] == b and best[l] == np.float32(resc[l][b])
+        else:
+            assert best_pose[l] == -1 and np.isinf(best[l])
+        if rmsd_min == 0.0:
+            assert np.array_equal(kept, live)
+    say(f"threshold flips: {flips}")
+    assert flips <= 1
