@@ -320,6 +320,75 @@ def rescore_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def knob_tuning(args):
+    """Bayesian tuning of (Q, T, S, passes, sweep_top) for the cheapest screen whose top 1 % keeps
+    args.knob_target of the reference search's top 1 % on a sample library; compared with random search
+    at the same number of screens and with every configuration of the grid."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2304_09953_amd import inputs as I
+    from paper_2304_09953_amd import knobs as K
+    from paper_2304_09953_amd import pipeline as P
+    W = I.workload("pocket96-lib100k")
+    pocket = W.pockets[0]
+    n_lig = args.n_lig or 4000
+    ligs = W.ligands(n_lig=n_lig)
+    dp = P.DevicePocket(pocket)
+    lib = P.DeviceLibrary(ligs)
+    cache = {}
+
+    def screen(srch):
+        scr = P.Screener(dp, lib, P.DeviceSearch(srch))
+        scr.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        scr.run()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3, scr.best_score.cpu().numpy().astype(np.float64)
+
+    t_ref, ref = screen(W.search)
+    ok = np.isfinite(ref)
+    k = max(1, int(round(0.01 * ok.sum())))
+    ids = np.flatnonzero(ok)
+    top_ref = set(ids[np.lexsort((ids, ref[ok]))[:k]].tolist())
+
+    def evaluate(cfg):
+        key = tuple(sorted(cfg.items()))
+        if key not in cache:
+            srch = dataclasses.replace(I.make_search(cfg["n_quat"], cfg["n_trans"], cfg["n_steps"], 4.0, pocket.center),
+                                       sweep_top=cfg["sweep_top"], passes=cfg["passes"])
+            t, best = screen(srch)
+            top = set(ids[np.lexsort((ids, best[ok]))[:k]].tolist())
+            cache[key] = (t / n_lig * 1e6, len(top & top_ref) / k)  # seconds per 1M ligands, recall
+        return cache[key]
+
+    target = args.knob_target
+    bo = K.optimize(evaluate, target, n_init=6, n_iter=args.knob_evals - 6, seed=0, log=log)
+    rnd = [K.random_search(evaluate, target, args.knob_evals, seed=s)["best"] for s in range(5)]
+    every = [{"cfg": c, "cost": evaluate(c)[0], "recall": evaluate(c)[1]} for c in K.grid()]
+    truth = K.best_feasible(every, target)
+    front = sorted(every, key=lambda h: h["cost"])
+    pareto, best_r = [], -1.0
+    for h in front:
+        if h["recall"] > best_r:
+            pareto.append(h)
+            best_r = h["recall"]
+    out = {"metric": "knob tuning: cheapest screen keeping the reference top 1 %", "unit": "s per 1M ligands",
+           "value": bo["best"]["cost"] if bo["best"] else None,
+           "config": {"workload": f"first {n_lig} ligands of {W.name}", "target_recall": target,
+                      "reference": "Q256 x T32, S256, one pass, every start",
+                      "reference_s_per_1M": t_ref / n_lig * 1e6, "screens_per_search": args.knob_evals,
+                      "grid_size": len(every)},
+           "bayesian": bo["best"], "bayesian_history": bo["history"],
+           "random_search_best": rnd, "grid_optimum": truth, "pareto_front": pareto}
+    print(json.dumps(out), flush=True)
+
+
 def budget_curve(args):
     """Speed and quality of the search-budget variants against the full search on the first
     args.n_lig (default 20000) ligands of the 100k workload: ligands/s, and per variant the mean
@@ -436,6 +505,10 @@ def main():
                     help="write the screen's counter summary from rocprofv3 --pmc CSV directories in DIR")
     ap.add_argument("--calibrate-peaks", choices=("all", "l2", "mall", "fma"), default=None,
                     help="measure the FMA rate and cache-resident read bandwidth of this GPU, then exit")
+    ap.add_argument("--tune-knobs", action="store_true",
+                    help="Bayesian tuning of the search knobs on --n-lig ligands (default 4000)")
+    ap.add_argument("--knob-target", type=float, default=0.9, help="recall of the reference top 1 %% to keep")
+    ap.add_argument("--knob-evals", type=int, default=30, help="screens per tuning search")
     ap.add_argument("--rescore", action="store_true",
                     help="pose filtering and rescoring after the screen on --n-lig ligands (default 20000)")
     ap.add_argument("--n-keep", type=int, default=8, help="poses kept per ligand before filtering (--rescore)")
@@ -499,6 +572,8 @@ def main():
         return batched_bench(args)
     if args.rescore:
         return rescore_bench(args)
+    if args.tune_knobs:
+        return knob_tuning(args)
     if args.prefilter:
         return prefilter_bench(args)
     W = I.workload("pocket96-lib100k")

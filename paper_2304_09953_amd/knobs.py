@@ -1,0 +1,148 @@
+"""Bayesian tuning of the search's quality knobs.
+
+The paper tunes the docking engine's quality/performance knobs with a Bayesian optimiser (§3.3,
+LiGen autotuning: a method aimed at the cheapest configuration of a recurring, constrained job).
+Here the knobs are the number of quaternions Q, of translations T, of torsion steps S, of greedy
+passes and of swept starts (sweep_top); the constraint is the recall of a reference ranking's top
+1 % on a sample library, the cost the screen's time per ligand.  The model is a Gaussian process
+per objective (log time, recall) over the knobs scaled to [0, 1] on a log2 axis; the next
+configuration maximises expected improvement of the time weighted by the probability that the
+recall constraint holds.  Candidates are the discrete grid of knob values; every evaluation is a
+real screen (the caller's `evaluate`).  Host-side logic only: it orders screens.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+SPACE = {"n_quat": (32, 64, 128, 256), "n_trans": (8, 16, 32), "n_steps": (64, 128, 256), "passes": (1, 2),
+         "sweep_top": (0, 64, 256, 1024)}
+
+
+def grid(space: dict = SPACE) -> list[dict]:
+    """Every combination; a sweep_top reaching Q*T means every start, so it collapses onto 0."""
+    out, seen = [], set()
+    keys = list(space)
+    for vals in itertools.product(*(space[k] for k in keys)):
+        c = dict(zip(keys, vals))
+        if c.get("sweep_top", 0) >= c["n_quat"] * c["n_trans"]:
+            c["sweep_top"] = 0
+        t = tuple(c[k] for k in keys)
+        if t not in seen:
+            seen.add(t)
+            out.append(c)
+    return out
+
+
+def encode(cfgs: list[dict], space: dict = SPACE) -> np.ndarray:
+    """Knob values on a log2 axis scaled to [0, 1] per knob (sweep_top 0, i.e. every start, sits at the
+    top of its axis, beyond the largest K)."""
+    cols = []
+    for k, vals in space.items():
+        if k == "sweep_top":
+            top = max(vals) * 4
+            f = lambda v: math.log2(v if v > 0 else top)  # noqa: E731
+            lo, hi = math.log2(min(v for v in vals if v > 0)), math.log2(top)
+        else:
+            f, lo, hi = math.log2, math.log2(min(vals)), math.log2(max(vals))
+        cols.append([(f(c[k]) - lo) / (hi - lo) if hi > lo else 0.0 for c in cfgs])
+    return np.array(cols, dtype=np.float64).T
+
+
+class GP:
+    """Gaussian process with a squared-exponential kernel, fixed length scale, standardised targets."""
+
+    def __init__(self, length: float = 0.4, noise: float = 1e-4):
+        self.length, self.noise = length, noise
+
+    def _k(self, A, B):
+        d2 = ((A[:, None, :] - B[None, :, :]) ** 2).sum(-1)
+        return np.exp(-0.5 * d2 / self.length ** 2)
+
+    def fit(self, X: np.ndarray, y: np.ndarray) -> "GP":
+        self.X = X
+        self.mu, self.sd = float(y.mean()), float(y.std()) or 1.0
+        z = (y - self.mu) / self.sd
+        K = self._k(X, X) + self.noise * np.eye(len(X))
+        self.L = np.linalg.cholesky(K)
+        self.alpha = np.linalg.solve(self.L.T, np.linalg.solve(self.L, z))
+        return self
+
+    def predict(self, Xs: np.ndarray):
+        Ks = self._k(Xs, self.X)
+        m = Ks @ self.alpha
+        v = np.linalg.solve(self.L, Ks.T)
+        var = np.maximum(1.0 - (v * v).sum(0), 1e-12)
+        return self.mu + self.sd * m, self.sd * np.sqrt(var)
+
+
+def _norm_cdf(z):
+    from scipy.stats import norm
+    return norm.cdf(z)
+
+
+def _norm_pdf(z):
+    from scipy.stats import norm
+    return norm.pdf(z)
+
+
+def constrained_ei(mu_c, sd_c, best_c, mu_r, sd_r, target):
+    """Expected improvement of the cost below best_c (+inf: none feasible yet, then the probability of
+    feasibility alone) times the probability that the recall reaches target."""
+    pf = _norm_cdf((mu_r - target) / sd_r)
+    if not np.isfinite(best_c):
+        return pf
+    z = (best_c - mu_c) / sd_c
+    return ((best_c - mu_c) * _norm_cdf(z) + sd_c * _norm_pdf(z)) * pf
+
+
+def optimize(evaluate, target: float, space: dict = SPACE, n_init: int = 6, n_iter: int = 20, seed: int = 0,
+             log=None) -> dict:
+    """Minimises cost subject to recall >= target.  evaluate(cfg) -> (cost, recall); cost > 0.
+    Returns the history and the best feasible configuration found."""
+    cands = grid(space)
+    X = encode(cands, space)
+    rng = np.random.default_rng(seed)
+    done, hist = [], []
+
+    def run(i):
+        cost, rec = evaluate(cands[i])
+        done.append(i)
+        hist.append({"cfg": cands[i], "cost": float(cost), "recall": float(rec)})
+        if log:
+            log(f"knobs {cands[i]}: cost {cost:.4g}, recall {rec:.3f}")
+
+    for i in rng.choice(len(cands), size=min(n_init, len(cands)), replace=False):
+        run(int(i))
+    for _ in range(n_iter):
+        if len(done) == len(cands):
+            break
+        Xd = X[done]
+        c = np.log(np.array([h["cost"] for h in hist]))
+        r = np.array([h["recall"] for h in hist])
+        feas = r >= target
+        best_c = c[feas].min() if feas.any() else np.inf
+        gp_c, gp_r = GP().fit(Xd, c), GP().fit(Xd, r)
+        rest = np.setdiff1d(np.arange(len(cands)), done)
+        mc, sc = gp_c.predict(X[rest])
+        mr, sr = gp_r.predict(X[rest])
+        acq = constrained_ei(mc, sc, best_c, mr, sr, target)
+        run(int(rest[int(np.argmax(acq))]))
+    return {"history": hist, "best": best_feasible(hist, target)}
+
+
+def random_search(evaluate, target: float, n: int, space: dict = SPACE, seed: int = 0) -> dict:
+    cands = grid(space)
+    rng = np.random.default_rng(seed)
+    hist = []
+    for i in rng.choice(len(cands), size=min(n, len(cands)), replace=False):
+        cost, rec = evaluate(cands[int(i)])
+        hist.append({"cfg": cands[int(i)], "cost": float(cost), "recall": float(rec)})
+    return {"history": hist, "best": best_feasible(hist, target)}
+
+
+def best_feasible(hist: list[dict], target: float):
+    ok = [h for h in hist if h["recall"] >= target]
+    return min(ok, key=lambda h: h["cost"]) if ok else None

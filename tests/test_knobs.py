@@ -1,0 +1,45 @@
+"""The knob tuner's host logic on a synthetic objective with a known constrained optimum."""
+import numpy as np
+
+from paper_2304_09953_amd import knobs as K
+
+
+def _synthetic(cfg):
+    # cost grows with the work; recall saturates with the work, more with passes and every start
+    work = cfg["n_quat"] * cfg["n_trans"] * cfg["n_steps"] / (32 * 8 * 64)
+    swept = 1.0 if cfg["sweep_top"] == 0 else min(1.0, cfg["sweep_top"] / (cfg["n_quat"] * cfg["n_trans"]))
+    cost = work * (0.1 + 0.9 * swept) * cfg["passes"] ** 0.8
+    recall = 1 - np.exp(-0.9 * np.log2(work * 2) * (0.5 + 0.5 * swept) * (1 + 0.15 * (cfg["passes"] - 1)))
+    return cost, recall
+
+
+def test_grid_collapses_selection_that_covers_every_start():
+    g = K.grid()
+    assert len(g) == len({tuple(c.values()) for c in g})
+    assert all(c["sweep_top"] < c["n_quat"] * c["n_trans"] for c in g)
+    X = K.encode(g)
+    assert X.shape == (len(g), 5) and X.min() >= 0 and X.max() <= 1
+
+
+def test_gp_interpolates_its_data():
+    rng = np.random.default_rng(0)
+    X = rng.random((12, 3))
+    y = np.sin(3 * X[:, 0]) + X[:, 1] ** 2
+    m, s = K.GP(length=0.5, noise=1e-8).fit(X, y).predict(X)
+    assert np.allclose(m, y, atol=1e-4) and np.all(s < 1e-2)
+
+
+def test_optimizer_finds_the_constrained_optimum():
+    target = 0.9
+    truth = K.best_feasible([{"cfg": c, "cost": _synthetic(c)[0], "recall": _synthetic(c)[1]} for c in K.grid()],
+                            target)
+    calls = []
+    res = K.optimize(lambda c: calls.append(c) or _synthetic(c), target, n_init=6, n_iter=24, seed=1)
+    assert len(calls) == 30 and len(K.grid()) > 150
+    best = res["best"]
+    assert best is not None and best["recall"] >= target
+    assert best["cost"] <= 1.10 * truth["cost"]
+    # and on average it does better than random search with the same number of screens
+    rnd = [K.random_search(_synthetic, target, 30, seed=s)["best"] for s in range(8)]
+    rnd_cost = np.mean([r["cost"] if r else np.inf for r in rnd])
+    assert best["cost"] <= rnd_cost
