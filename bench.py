@@ -81,7 +81,7 @@ def summarize_counters(out_dir):
     valu = one("pmc_valu", "SQ_INSTS_VALU")
     gui = one("pmc_valu", "GRBM_GUI_ACTIVE")  # summed over the 8 XCDs
     hit, miss = one("pmc_req", "TCC_HIT_sum"), one("pmc_req", "TCC_MISS_sum")
-    base = "cd /tmp && rocprofv3 --pmc {c} -T -f csv -d <repo>/gpurun_out/{d} -o {o} -- python3 -u <repo>/bench.py {a}"
+    base = "cd /tmp && rocprofv3 --pmc {c} -T -f csv -d <out>/{d} -o {o} -- python3 -u <repo>/bench.py {a}"
     run1 = "--no-cpu-baseline --steps 1 --warmup 0"
     out = {
         "kernel": "k_screen",

@@ -414,3 +414,52 @@ def test_pocket96_lib100k_sample_full_search(P):
     orc = oracle.dock(pocket, G, ligs, W.search, sel=loc, per_start=True)
     check_optimal(pocket, G, ligs, W.search, loc, g["score"][loc], g["start"][loc], orc)
     assert g["poses"] == oracle.pose_count(ligs.n_rot, g["status"], W.search.n_starts, W.search.n_steps)
+
+
+@pytest.mark.parametrize("S", [300, 1024])
+def test_screen_many_steps(P, S):
+    # 300 steps: five 64-lane angle groups per lane; 1024 (the limit): sixteen
+    pocket = I.make_pocket(40, 4, pocket_id=13)
+    G = oracle.build_grids(pocket)
+    ligs = I.make_ligands(6, I.DIST_DRUGLIKE, 4, stream="test", first_id=3000)
+    srch = I.make_search(4, 2, S, 3.0, pocket.center)
+    say(f"screen 6 ligands, 8 starts, S={S}")
+    dp = P.DevicePocket(pocket)
+    g = _screen(P, dp, ligs, srch, start_scores=True)
+    orc = oracle.dock(pocket, G, ligs, srch, per_start=True)
+    st = check_per_start(pocket, G, ligs, srch, g["finals"], g["start_steps"], orc)
+    say(f"per-start: {st}")
+    assert st["agree"] >= 0.95 * st["starts"]
+    sel = np.arange(ligs.n_lig)
+    check_exact_and_valid(pocket, G, ligs, srch, sel, g["score"], g["start"], g["steps"])
+    check_optimal(pocket, G, ligs, srch, sel, g["score"], g["start"], orc)
+    assert np.all(g["steps"] < S)
+
+
+def test_start_selection_at_full_size(P):
+    import dataclasses
+    W = I.workload("pocket96-lib100k")
+    pocket = W.pockets[0]
+    ligs = W.ligands(n_lig=200).subset(np.array([3, 50, 121, 199]))
+    srch = dataclasses.replace(W.search, sweep_top=256)
+    QT = srch.n_starts
+    say("sweep_top 256 of 8192 starts, 4 ligands of the 100k workload")
+    dp = P.DevicePocket(pocket)
+    G = oracle.build_grids(pocket)
+    g = _screen(P, dp, ligs, srch, start_scores=True)
+    searched = np.isfinite(g["finals"])
+    assert np.all(searched.sum(1) == 256)
+    for l in range(ligs.n_lig):
+        rig = oracle.score_poses(pocket, G, ligs, srch, np.full(QT, l), np.arange(QT), np.zeros((QT, 16), int))
+        lim = tol_fp32(rig, ligs.n_atoms[l], G, pocket.dims).max()
+        assert rig[searched[l]].max() <= rig[~searched[l]].min() + 2 * lim
+    # the searched starts' finals against the oracle's greedy from those starts
+    li, pi = np.nonzero(searched)
+    gs = oracle.greedy_starts(pocket, G, ligs, srch, li, pi)
+    f_gpu = g["finals"][li, pi]
+    bound = tol_fp32(gs["final"], ligs.n_atoms[li], G, pocket.dims)
+    agree = np.abs(f_gpu - gs["final"]) <= bound
+    say(f"{agree.sum()} of {len(agree)} searched starts agree; the rest must be near-tie paths")
+    assert agree.mean() >= 0.98
+    assert np.all(gs["gap"][~agree] < 1e-3)
+    assert g["poses"] == int(np.sum(QT + 256 * ligs.n_rot * (srch.n_steps - 1)))
