@@ -198,6 +198,13 @@ __device__ __forceinline__ bool mask_has(const uint4 &m, int i) {
     return (w >> (i & 31)) & 1u;
 }
 
+// mask_has for atom lane + 64 h of a wavefront (lane < 64; h is 0 or 1, usually a constant of an
+// unrolled loop), selecting between two words instead of four.
+__device__ __forceinline__ bool mask_has_lane(const uint4 &m, int h, int lane) {
+    const uint32_t w = h == 0 ? (lane < 32 ? m.x : m.y) : (lane < 32 ? m.z : m.w);
+    return (w >> (lane & 31)) & 1u;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Radix sort of 64-bit keys (stable LSD, 8-bit digits), shared by the screen planner and top-k
 // ---------------------------------------------------------------------------------------------

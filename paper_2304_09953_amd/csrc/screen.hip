@@ -381,7 +381,7 @@ __device__ __forceinline__ void axis(const TorRec &tr, const float (&cx)[2], con
     ux = xbx - xax;
     uy = xby - xay;
     uz = xbz - xaz;
-    const float un = 1.0f / sqrtf(fmaf(ux, ux, fmaf(uy, uy, uz * uz)));
+    const float un = __builtin_amdgcn_rsqf(fmaf(ux, ux, fmaf(uy, uy, uz * uz)));  // 1 ulp
     ux *= un;
     uy *= un;
     uz *= un;
@@ -466,7 +466,7 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
             const int jj = lane + kWave * h2;
             zj[h2] = 0.0f;
             rj[h2] = INFINITY;
-            if (jj < n && !mask_has(mask, jj)) {
+            if (jj < n && !mask_has_lane(mask, h2, lane)) {
                 const float vx = cx[h2] - xax, vy = cy[h2] - xay, vz = cz[h2] - xaz;
                 zj[h2] = fmaf(ux, vx, fmaf(uy, vy, uz * vz));
                 const float ox = fmaf(-zj[h2], ux, vx), oy = fmaf(-zj[h2], uy, vy), oz = fmaf(-zj[h2], uz, vz);
@@ -513,7 +513,7 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
         for (int h = 0; h < 2; ++h) {
             if (kWave * h >= n) break;
             const int i = lane + kWave * h;
-            const bool mv = i < n && mask_has(mask, i);
+            const bool mv = i < n && mask_has_lane(mask, h, lane);
             const uint64_t bal = __ballot(mv);
             const int cnt = __popcll(bal);
             if (mv) {
@@ -592,7 +592,7 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
                     if (kWave * h2 >= n) break;
                     const int jj = lane + kWave * h2;
                     const float dr = rho - rj[h2], dz = zq - zj[h2];
-                    const bool keep = fmaf(dr, dr, dz * dz) < s.cut2_keep && !mask_has(ex, jj);
+                    const bool keep = fmaf(dr, dr, dz * dz) < s.cut2_keep && !mask_has_lane(ex, h2, lane);
                     const uint64_t kb = __ballot(keep);
                     if (keep) W.sidx[nsurv + lanes_below(kb)] = (uint16_t)(q | (jj << 8));
                     nsurv += __popcll(kb);
