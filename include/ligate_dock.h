@@ -61,13 +61,15 @@ extern "C" {
 #define DOCK_MAX_PASSES 16
 
 #define DOCK_LAYOUT_LINEAR 0     /* grids [t][z][y][x], FP32, x fastest */
-#define DOCK_LAYOUT_XY4 1        /* per node a 16-byte record of its z plane: G(x, y),
-                                    G(x+1, y) - G(x, y), G(x, y+1), G(x+1, y+1) - G(x, y+1)
-                                    (differences rounded to FP32; indices beyond the last node wrap
-                                    to 0), stored as [t][z/2][y/2][x][z&1][y&1] with dimensions
-                                    rounded up to even, so that a 128-byte line holds 2 x 2 x 2
-                                    records; about 4x the memory, and a trilinear lookup reads two
-                                    records, mostly from one line */
+#define DOCK_LAYOUT_XY4 1        /* per node a 16-byte record of its z plane: G00 = G(x, y),
+                                    dX = G(x+1, y) - G00, dY = G(x, y+1) - G00,
+                                    dXY = (G(x+1, y+1) - G(x, y+1)) - dX (differences rounded to
+                                    FP32; indices beyond the last node wrap to 0), stored as
+                                    [t][z/2][y/2][x][z&1][y&1] with dimensions rounded up to even,
+                                    so that a 128-byte line holds 2 x 2 x 2 records; about 4x the
+                                    memory, and a trilinear lookup reads two records, mostly from
+                                    one line.  Requires (nx rounded up to even) * ceil(ny / 2)
+                                    <= 2^18 */
 #define DOCK_BOUNDARY_CLAMP 0    /* clamp into the box + w_out * |x - clamp(x)|^2 */
 #define DOCK_BOUNDARY_PERIODIC 1 /* indices wrap modulo the grid size */
 

@@ -1,6 +1,6 @@
 // Receptor grid build: one thread per (atom type, node), FP64 sum over the protein atoms,
 // capped, stored in FP32 as [t][z][y][x] (linear layout) or scattered into the four xy4 records
-// that hold the node (xy4 layout, bricked record order), whose x differences a second pass forms.
+// that hold the node (xy4 layout, bricked record order), whose differences a second pass forms.
 #include "common.h"
 
 namespace ligate {
@@ -68,8 +68,9 @@ __global__ __launch_bounds__(kGridBlock) void k_build_grids(int nx, int ny, int 
     base[geo.offset(im, jm, k) / 4 + 3] = v;
 }
 
-// xy4 records (a, b, c, d) -> (a, b - a, c, d - c), in FP32 as the interpolation would form them;
-// the padding records of odd dimensions (never read) are set to zero.
+// xy4 records of node values (a, b, c, d) = (G00, G10, G01, G11) -> the plane form (a, b - a, c - a,
+// (d - c) - (b - a)), rounded in FP32 exactly as the linear layout's lookups form it; the padding
+// records of odd dimensions (never read) are set to zero.
 __global__ __launch_bounds__(kGridBlock) void k_xy4_diff(float4 *__restrict__ rec, int64_t n, int nx, int ny, int nz) {
     const int64_t i = (int64_t)blockIdx.x * kGridBlock + threadIdx.x;
     if (i >= n) return;
@@ -80,8 +81,8 @@ __global__ __launch_bounds__(kGridBlock) void k_xy4_diff(float4 *__restrict__ re
     const uint32_t y = 2u * ((brick / geo.nxp) % geo.nby) + (pos & 1u);
     const uint32_t z = 2u * (brick / (geo.nxp * geo.nby)) + (pos >> 1);
     float4 r = rec[i];
-    r.y = r.y - r.x;
-    r.w = r.w - r.z;
+    const float dx = r.y - r.x;
+    r = make_float4(r.x, dx, r.z - r.x, (r.w - r.z) - dx);
     if (x >= (uint32_t)nx || y >= (uint32_t)ny || z >= (uint32_t)nz) r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     rec[i] = r;
 }
@@ -99,6 +100,13 @@ static int check_desc(const dock_grid_desc *g) {
     LIGATE_REQUIRE(grid_type_bytes(g) * (uint64_t)g->n_types < (1ull << 31), DOCK_ERR_LIMIT,
                    "grids of all types reach 2^31 bytes");
     LIGATE_REQUIRE(grid_type_bytes(g) < (1ull << 28), DOCK_ERR_LIMIT, "one type grid reaches 2^28 bytes");
+    if (g->layout == DOCK_LAYOUT_XY4) {
+        // the record offsets take 24-bit multiplies by the strides of y and z pairs (64 nxp - 32
+        // and 64 nxp nby - 64)
+        const Xy4Geom geo = Xy4Geom::of(g->nx, g->ny, g->nz);
+        LIGATE_REQUIRE(64ull * geo.nxp * geo.nby <= (1ull << 24), DOCK_ERR_LIMIT,
+                       "xy4 layout: (nx rounded up to even) * ceil(ny / 2) exceeds 2^18");
+    }
     LIGATE_REQUIRE(g->boundary == DOCK_BOUNDARY_CLAMP || g->boundary == DOCK_BOUNDARY_PERIODIC,
                    DOCK_ERR_INVALID_ARG, "unknown boundary mode %d", g->boundary);
     return DOCK_OK;

@@ -1,12 +1,16 @@
 // The docking screen: rigid starts, greedy torsion sweeps, best pose per ligand.
 //
 // Work decomposition.  A work item is (ligand, batch of rigid starts).  Persistent blocks pop
-// items from an atomic counter; items are ordered by descending estimated cost so the longest
-// ligands start first.  A block stages the item's ligand in LDS and its wavefronts take the
+// items from an atomic counter.  Starts are enumerated translation-major (a batch of n_quat
+// starts shares one translation) and items run batch-major, each batch over the ligands in
+// order of descending estimated cost: at any time the whole chip works around the same
+// translation, so the grid region it reads is about one ligand's extent, which keeps more of
+// it in the L2 caches.  A block stages the item's ligand in LDS and its wavefronts take the
 // item's starts round-robin.  Within a wavefront, lanes are torsion steps: lane L evaluates the
 // angles 2 pi (L + 64 j) / S, j < APL, so one sweep of S angles costs ceil(S / 64) angles per
-// lane and the argmin is a single wave reduction.  Atom coordinates live in registers, atom i
-// (and i + 64) on lane i.
+// lane and the argmin is a single wave reduction.  A start's atom coordinates live in a
+// per-wavefront LDS copy (atom i read by lane i and i - 64), which keeps the sweep's registers
+// for the lookups.
 //
 // Scoring inside a sweep.  Turning torsion k moves only its moving set M_k, so the step that
 // minimises the score also minimises the part that depends on the step: the grid terms of the
@@ -40,13 +44,14 @@ struct GridC {
     // below 2^26 and multiples of 4, so exact in FP32)
     uint32_t row, plane;
     float frow, fplane;
-    // xy4 layout: the record offset is 64 x + 16 y + 32 z + ky (y >> 1) + kz (z >> 1) (exact in
-    // FP32: multiples of 16 below 2^28); the z + 1 record is 32 bytes further for even z and
-    // dz_odd further for odd z
+    // xy4 layout: the record offset is 64 x + 16 y + 32 z + ky (y >> 1) + kz (z >> 1), and the
+    // z + 1 record sits at 64 x + 16 y + 32 (z + 1) + ky (y >> 1) + kz ((z + 1) >> 1) with
+    // (z + 1) >> 1 = z - (z >> 1); ky, kz < 2^24 (checked with the descriptor), so the products
+    // take 24-bit multiplies
     Xy4Geom geo;
-    float ky, kz;
-    uint32_t dz_odd;
+    uint32_t ky, kz;
     float mx, my, mz;          // n - 1: clamp bound
+    float in_lo, in_x, in_y, in_z;  // inside-the-box test: [kEdge, n - 1 - kEdge] per axis
     float cx, cy, cz;          // n - 2: last cell
     float inv_h, ox_h, oy_h, oz_h;  // grid units: u = x / h - o / h
     float w_h2;                // restraint weight in grid units (w_out h^2)
@@ -82,6 +87,7 @@ struct Coef {
 };
 static_assert(sizeof(Coef) == 48, "Coef layout");
 constexpr uint32_t kInside = 0x80000000u;
+constexpr float kEdge = 1e-3f;  // margin of the inside-the-box test, in grid units
 
 constexpr int kSurvCap = 128;
 
@@ -90,7 +96,7 @@ struct WaveLDS {
     uint8_t atom[kWave];
     uint16_t sidx[kSurvCap];      // surviving pair: moving slot q | fixed atom j << 8
     float4 surv[kSurvCap];        // its distance coefficients (A, C, D)
-    float4 pos[DOCK_MAX_ATOMS];   // current coordinates, written at the start of each sweep
+    float3 pos[DOCK_MAX_ATOMS];   // the start's current coordinates (grid units)
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -112,57 +118,90 @@ __device__ __forceinline__ float ld1(rsrc_t rs, uint32_t voff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, 0, 0));
 }
 
-// Trilinear interpolation as linear interpolations along x, then y, then z; a/b are the x pairs
-// of rows (y0, z0)/(y1, z0), c/d of rows (y0, z1)/(y1, z1).
-__device__ __forceinline__ float trilerp(float fx, float fy, float fz, float2 a, float2 b, float2 c, float2 d) {
-    const float c00 = fmaf(fx, a.y - a.x, a.x), c10 = fmaf(fx, b.y - b.x, b.x);
-    const float c01 = fmaf(fx, c.y - c.x, c.x), c11 = fmaf(fx, d.y - d.x, d.x);
-    const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
+// Trilinear interpolation from the two z planes of a cell, each given as (G00, dX, dY, dXY) with
+// G00 = G(x0, y0), dX = G(x1, y0) - G00, dY = G(x0, y1) - G00 and dXY = (G(x1, y1) - G(x0, y1)) - dX,
+// all differences rounded to FP32: a plane is G00 + fx dX + fy (dY + fx dXY), then a lerp along z.
+__device__ __forceinline__ float plane(float fx, float fy, const float4 &r) {
+    return fmaf(fy, fmaf(fx, r.w, r.z), fmaf(fx, r.y, r.x));
+}
+
+__device__ __forceinline__ float trilerp(float fx, float fy, float fz, const float4 &p0, const float4 &p1) {
+    const float c0 = plane(fx, fy, p0), c1 = plane(fx, fy, p1);
     return fmaf(fz, c1 - c0, c0);
 }
 
-// The same with the x pairs given as (G(x0), G(x0 + 1) - G(x0)), the difference rounded to FP32
-// exactly as trilerp forms it, so both give identical results.
-__device__ __forceinline__ float trilerp_dx(float fx, float fy, float fz, float2 a, float2 b, float2 c, float2 d) {
-    const float c00 = fmaf(fx, a.y, a.x), c10 = fmaf(fx, b.y, b.x);
-    const float c01 = fmaf(fx, c.y, c.x), c11 = fmaf(fx, d.y, d.x);
-    const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
-    return fmaf(fz, c1 - c0, c0);
+// The plane form of the corners (G00, G10) = a, (G01, G11) = b, rounded exactly as the xy4 grid
+// build forms its records, so both layouts interpolate identically.
+__device__ __forceinline__ float4 plane_of(float2 a, float2 b) {
+    const float dx = a.y - a.x;
+    return make_float4(a.x, dx, b.x - a.x, (b.y - b.x) - dx);
 }
 
-// Cell byte offset and fractions of grid point u; dz receives the distance in bytes from the
-// (x0, y0, z0) record to the (x0, y0, z0 + 1) record (xy4 layout).  INSIDE: the caller guarantees
-// 0 <= u <= n - 1 - margin, where clamping is the identity and the restraint vanishes, so both
-// variants give the same value there.
+// v_cvt_flr_i32_f32: floor and conversion in one instruction (exact for the in-box coordinates it
+// is used on).
+__device__ __forceinline__ uint32_t floor_u32(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return (uint32_t)r;
+}
+
+// Cell byte offset and fractions of grid point u.  off2 receives, in the xy4 layout, the byte
+// offset of the (x0, y0, z0 + 1) record minus 32 (the loads add the 32 as an immediate).
+// INSIDE: the caller guarantees 0 <= u <= n - 1 - margin, where clamping is the identity and the
+// restraint vanishes, so both variants give the same value there.
 template <bool INSIDE, int LAYOUT>
 __device__ __forceinline__ uint32_t cell(const GridC &g, float ux, float uy, float uz, float &fx, float &fy, float &fz,
-                                         float &rest, uint32_t &dz) {
-    float qx = ux, qy = uy, qz = uz, x0, y0, z0;
-    if constexpr (INSIDE) {
-        x0 = floorf(qx);
-        y0 = floorf(qy);
-        z0 = floorf(qz);
-        rest = 0.0f;
-    } else {
-        // fmaxf returns the non-NaN operand, so even a NaN coordinate yields an in-range cell
-        qx = fminf(fmaxf(ux, 0.0f), g.mx);
-        qy = fminf(fmaxf(uy, 0.0f), g.my);
-        qz = fminf(fmaxf(uz, 0.0f), g.mz);
-        x0 = floorf(fminf(qx, g.cx));
-        y0 = floorf(fminf(qy, g.cy));
-        z0 = floorf(fminf(qz, g.cz));
-        const float dx = ux - qx, dy = uy - qy, dz = uz - qz;
-        rest = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    }
-    fx = qx - x0;
-    fy = qy - y0;
-    fz = qz - z0;
+                                         float &rest, uint32_t &off2) {
     if constexpr (LAYOUT == DOCK_LAYOUT_XY4) {
-        const float by = floorf(0.5f * y0), bz = floorf(0.5f * z0);
-        dz = z0 != 2.0f * bz ? g.dz_odd : 32u;
-        return (uint32_t)fmaf(x0, 64.0f, fmaf(y0, 16.0f, fmaf(by, g.ky, fmaf(z0, 32.0f, bz * g.kz))));
+        uint32_t x, y, z;
+        if constexpr (INSIDE) {
+            // u >= 0: u - floor(u) is exact, and v_fract_f32 returns it
+            x = floor_u32(ux);
+            y = floor_u32(uy);
+            z = floor_u32(uz);
+            fx = __builtin_amdgcn_fractf(ux);
+            fy = __builtin_amdgcn_fractf(uy);
+            fz = __builtin_amdgcn_fractf(uz);
+            rest = 0.0f;
+        } else {
+            // fmaxf returns the non-NaN operand, so even a NaN coordinate yields an in-range cell
+            const float qx = fminf(fmaxf(ux, 0.0f), g.mx), qy = fminf(fmaxf(uy, 0.0f), g.my),
+                        qz = fminf(fmaxf(uz, 0.0f), g.mz);
+            const float x0 = floorf(fminf(qx, g.cx)), y0 = floorf(fminf(qy, g.cy)), z0 = floorf(fminf(qz, g.cz));
+            fx = qx - x0;
+            fy = qy - y0;
+            fz = qz - z0;
+            x = (uint32_t)x0;
+            y = (uint32_t)y0;
+            z = (uint32_t)z0;
+            const float dx = ux - qx, dy = uy - qy, dz = uz - qz;
+            rest = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        }
+        const uint32_t hy = (y >> 1) & 0x7fffffu, hz = (z >> 1) & 0x7fffffu, hz1 = (z - hz) & 0xffffffu;
+        const uint32_t t = __umul24(hy, g.ky) + (x << 6) + (y << 4) + (z << 5);
+        off2 = __umul24(hz1, g.kz) + t;
+        return __umul24(hz, g.kz) + t;
     } else {
-        dz = g.plane;
+        float qx = ux, qy = uy, qz = uz, x0, y0, z0;
+        if constexpr (INSIDE) {
+            x0 = floorf(qx);
+            y0 = floorf(qy);
+            z0 = floorf(qz);
+            rest = 0.0f;
+        } else {
+            qx = fminf(fmaxf(ux, 0.0f), g.mx);
+            qy = fminf(fmaxf(uy, 0.0f), g.my);
+            qz = fminf(fmaxf(uz, 0.0f), g.mz);
+            x0 = floorf(fminf(qx, g.cx));
+            y0 = floorf(fminf(qy, g.cy));
+            z0 = floorf(fminf(qz, g.cz));
+            const float dx = ux - qx, dy = uy - qy, dz = uz - qz;
+            rest = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        }
+        fx = qx - x0;
+        fy = qy - y0;
+        fz = qz - z0;
+        off2 = 0;
         return (uint32_t)fmaf(z0, g.fplane, fmaf(y0, g.frow, 4.0f * x0));
     }
 }
@@ -171,33 +210,22 @@ __device__ __forceinline__ float4 ld4(rsrc_t rs, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, 0));
 }
 
-// The four x pairs of a cell whose base node is at byte offset `off` (+ soff): linear layout,
-// one 8-byte load per (y, z) row, as (G(x0), G(x0 + 1)); xy4 layout, one 16-byte record per z
-// plane, the second `dz` bytes after the first, as (G(x0), G(x0 + 1) - G(x0)).
+// The two z planes of a cell whose base node is at byte offset `off` (+ soff) in plane form:
+// xy4 layout, the stored records (the second at off2 + 32); linear layout, one 8-byte load per
+// (y, z) row, with the differences formed here.
 struct CellVals {
-    float2 a, b, c, d;
+    float4 p0, p1;
 };
 
 template <int LAYOUT>
-__device__ __forceinline__ float interp(float fx, float fy, float fz, const CellVals &v) {
-    if constexpr (LAYOUT == DOCK_LAYOUT_XY4) return trilerp_dx(fx, fy, fz, v.a, v.b, v.c, v.d);
-    return trilerp(fx, fy, fz, v.a, v.b, v.c, v.d);
-}
-
-template <int LAYOUT>
-__device__ __forceinline__ CellVals load_cell(const GridC &g, rsrc_t rs, uint32_t off, uint32_t dz, uint32_t soff) {
+__device__ __forceinline__ CellVals load_cell(const GridC &g, rsrc_t rs, uint32_t off, uint32_t off2, uint32_t soff) {
     CellVals v;
     if constexpr (LAYOUT == DOCK_LAYOUT_XY4) {
-        const float4 r0 = ld4(rs, off, soff), r1 = ld4(rs, off + dz, soff);
-        v.a = make_float2(r0.x, r0.y);
-        v.b = make_float2(r0.z, r0.w);
-        v.c = make_float2(r1.x, r1.y);
-        v.d = make_float2(r1.z, r1.w);
+        v.p0 = ld4(rs, off, soff);
+        v.p1 = ld4(rs, off2 + 32u, soff);
     } else {
-        v.a = ld2(rs, off, soff);
-        v.b = ld2(rs, off, soff + g.row);
-        v.c = ld2(rs, off, soff + g.plane);
-        v.d = ld2(rs, off, soff + g.plane + g.row);
+        v.p0 = plane_of(ld2(rs, off, soff), ld2(rs, off, soff + g.row));
+        v.p1 = plane_of(ld2(rs, off, soff + g.plane), ld2(rs, off, soff + g.plane + g.row));
     }
     return v;
 }
@@ -207,17 +235,17 @@ __device__ __forceinline__ CellVals load_cell(const GridC &g, rsrc_t rs, uint32_
 template <int N, bool INSIDE, int LAYOUT>
 __device__ __forceinline__ void lookup_group(const GridC &g, rsrc_t rs, const uint32_t (&sof)[N], const float (&ux)[N],
                                              const float (&uy)[N], const float (&uz)[N], float (&out)[N]) {
-    uint32_t off[N], dz[N];
+    uint32_t off[N], off2[N];
     float fx[N], fy[N], fz[N], rest[N];
 #pragma unroll
     for (int k = 0; k < N; ++k)
-        off[k] = cell<INSIDE, LAYOUT>(g, ux[k], uy[k], uz[k], fx[k], fy[k], fz[k], rest[k], dz[k]);
+        off[k] = cell<INSIDE, LAYOUT>(g, ux[k], uy[k], uz[k], fx[k], fy[k], fz[k], rest[k], off2[k]);
     CellVals cv[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) cv[k] = load_cell<LAYOUT>(g, rs, off[k], dz[k], sof[k]);
+    for (int k = 0; k < N; ++k) cv[k] = load_cell<LAYOUT>(g, rs, off[k], off2[k], sof[k]);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const float v = interp<LAYOUT>(fx[k], fy[k], fz[k], cv[k]);
+        const float v = trilerp(fx[k], fy[k], fz[k], cv[k].p0, cv[k].p1);
         out[k] = INSIDE ? v : fmaf(g.w_h2, rest[k], v);
     }
 }
@@ -227,10 +255,10 @@ template <int BOUNDARY, int LAYOUT>
 __device__ __forceinline__ float lookup_lane(const GridC &g, rsrc_t rs, uint32_t tof, float ux, float uy, float uz) {
     if constexpr (BOUNDARY == DOCK_BOUNDARY_CLAMP) {
         float fx, fy, fz, rest;
-        uint32_t dz;
-        const uint32_t off = cell<false, LAYOUT>(g, ux, uy, uz, fx, fy, fz, rest, dz) + tof;
-        const CellVals v = load_cell<LAYOUT>(g, rs, off, dz, 0);
-        return fmaf(g.w_h2, rest, interp<LAYOUT>(fx, fy, fz, v));
+        uint32_t off2;
+        const uint32_t off = cell<false, LAYOUT>(g, ux, uy, uz, fx, fy, fz, rest, off2) + tof;
+        const CellVals v = load_cell<LAYOUT>(g, rs, off, off2 + tof, 0);
+        return fmaf(g.w_h2, rest, trilerp(fx, fy, fz, v.p0, v.p1));
     } else if constexpr (LAYOUT == DOCK_LAYOUT_XY4) {
         // records wrap in x and y; the z neighbour is the record of plane jz
         const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
@@ -240,10 +268,7 @@ __device__ __forceinline__ float lookup_lane(const GridC &g, rsrc_t rs, uint32_t
         iy += iy < 0 ? g.ny : 0;
         iz += iz < 0 ? g.nz : 0;
         const int jz = iz + 1 == g.nz ? 0 : iz + 1;
-        const float4 r0 = ld4(rs, tof + g.geo.offset(ix, iy, iz), 0);
-        const float4 r1 = ld4(rs, tof + g.geo.offset(ix, iy, jz), 0);
-        return trilerp_dx(fx, fy, fz, make_float2(r0.x, r0.y), make_float2(r0.z, r0.w), make_float2(r1.x, r1.y),
-                          make_float2(r1.z, r1.w));
+        return trilerp(fx, fy, fz, ld4(rs, tof + g.geo.offset(ix, iy, iz), 0), ld4(rs, tof + g.geo.offset(ix, iy, jz), 0));
     } else {
         const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
         const float fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
@@ -261,7 +286,7 @@ __device__ __forceinline__ float lookup_lane(const GridC &g, rsrc_t rs, uint32_t
         const float2 b = make_float2(ld1(rs, r10 + 4 * ix), ld1(rs, r10 + 4 * jx));
         const float2 c = make_float2(ld1(rs, r01 + 4 * ix), ld1(rs, r01 + 4 * jx));
         const float2 d = make_float2(ld1(rs, r11 + 4 * ix), ld1(rs, r11 + 4 * jx));
-        return trilerp(fx, fy, fz, a, b, c, d);
+        return trilerp(fx, fy, fz, plane_of(a, b), plane_of(c, d));
     }
 }
 
@@ -387,6 +412,27 @@ __device__ __forceinline__ void axis(const TorRec &tr, const float (&cx)[2], con
     uz *= un;
 }
 
+// The same axis from the wave's LDS copy of the coordinates; the values are wave-uniform and are
+// moved to scalar registers.
+__device__ __forceinline__ float uniform_f(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ void axis_lds(const TorRec &tr, const WaveLDS &W, float &xax, float &xay, float &xaz,
+                                         float &ux, float &uy, float &uz) {
+    const float3 xa = W.pos[tr.a], xb = W.pos[tr.b];
+    ux = xb.x - xa.x;
+    uy = xb.y - xa.y;
+    uz = xb.z - xa.z;
+    const float un = __builtin_amdgcn_rsqf(fmaf(ux, ux, fmaf(uy, uy, uz * uz)));  // 1 ulp
+    xax = uniform_f(xa.x);
+    xay = uniform_f(xa.y);
+    xaz = uniform_f(xa.z);
+    ux = uniform_f(ux * un);
+    uy = uniform_f(uy * un);
+    uz = uniform_f(uz * un);
+}
+
 // Score of the conformer in registers from scratch: every atom's grid term and every clash pair.
 template <int BOUNDARY, int LAYOUT>
 __device__ float direct_score(const GridC &g, rsrc_t rs, const SearchC &s, const LigLDS &L, const float (&cx)[2],
@@ -419,20 +465,28 @@ __device__ float direct_score(const GridC &g, rsrc_t rs, const SearchC &s, const
 }
 
 // The greedy passes from rigid start p.  Returns the final score (identical on all lanes);
-// lane k (< B) receives torsion k's total turn over the passes (modulo S) in `my_step`.
+// lane k (< B) receives torsion k's total turn over the passes (modulo S) in `my_step`.  The
+// start's coordinates live in the wave's LDS copy W.pos (atom i at W.pos[i]), not in registers, so
+// that the lookups of a sweep run with fewer live registers.
 template <int APL, int BOUNDARY, int LAYOUT>
 __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const LigLDS &L, WaveLDS &W, int p,
                            float clash_ref, const float (&cs)[APL], const float (&sn)[APL], int &my_step) {
     const int lane = lane_id();
     const int n = L.n;
-    float cx[2], cy[2], cz[2];
-    place(g, s, L, p, cx, cy, cz);
     float eg = 0.0f;
+    {
+        float cx[2], cy[2], cz[2];
+        place(g, s, L, p, cx, cy, cz);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int i = lane + kWave * h;
-        if (i < n) eg += lookup_lane<BOUNDARY, LAYOUT>(g, rs, L.tof[i], cx[h], cy[h], cz[h]);
+        for (int h = 0; h < 2; ++h) {
+            const int i = lane + kWave * h;
+            if (i < n) {
+                eg += lookup_lane<BOUNDARY, LAYOUT>(g, rs, L.tof[i], cx[h], cy[h], cz[h]);
+                W.pos[i] = make_float3(cx[h], cy[h], cz[h]);
+            }
+        }
     }
+    wave_sync();
     float E = wave_sum(eg) + clash_ref;
     // The score is carried incrementally in FP32; when it passed through values much larger than
     // the final one (atoms far outside the box or clashing in the rigid pose), the cancellation
@@ -442,7 +496,6 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
     // lookups are grouped four at a time: NJ angles of NA moving atoms
     constexpr int NJ = APL < 4 ? APL : 4;
     constexpr int NA = 4 / NJ;
-    const float edge = 1e-3f;  // margin of the inside-the-box test, in grid units
 
     my_step = 0;
     // the sweeps of all passes: torsion k runs 0..B-1 in every pass
@@ -450,7 +503,7 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
         const TorRec tr = L.tor[k];
         const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
         float xax, xay, xaz, ux, uy, uz;
-        axis(tr, cx, cy, cz, xax, xay, xaz, ux, uy, uz);
+        axis_lds(tr, W, xax, xay, xaz, ux, uy, uz);
 
         // angles past S start at +inf, so they never win the argmin
         float e[APL];
@@ -458,30 +511,13 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
         for (int j = 0; j < APL; ++j) e[j] = lane + kWave * j < s.S ? 0.0f : INFINITY;
         int nsurv = 0, nbuilt = 0;
 
-        // fixed atoms: cylinder coordinates about the axis (radius +inf for the others, so that
-        // no pair with them passes the closest-approach test) and coordinates for the pair terms
-        float zj[2], rj[2];
-#pragma unroll
-        for (int h2 = 0; h2 < 2; ++h2) {
-            const int jj = lane + kWave * h2;
-            zj[h2] = 0.0f;
-            rj[h2] = INFINITY;
-            if (jj < n && !mask_has_lane(mask, h2, lane)) {
-                const float vx = cx[h2] - xax, vy = cy[h2] - xay, vz = cz[h2] - xaz;
-                zj[h2] = fmaf(ux, vx, fmaf(uy, vy, uz * vz));
-                const float ox = fmaf(-zj[h2], ux, vx), oy = fmaf(-zj[h2], uy, vy), oz = fmaf(-zj[h2], uz, vz);
-                rj[h2] = __builtin_amdgcn_sqrtf(fmaf(ox, ox, fmaf(oy, oy, oz * oz)));
-            }
-            if (jj < n) W.pos[jj] = make_float4(cx[h2], cy[h2], cz[h2], 0.0f);
-        }
-
         // distance coefficients of the survivors [nbuilt, nsurv), whose moving slots refer to
         // the coefficients currently in W.coef: d^2(t) = A + C cos t + D sin t
         auto build = [&]() {
             for (int i = nbuilt + lane; i < nsurv; i += kWave) {
                 const uint32_t id = W.sidx[i];
                 const Coef c = W.coef[id & 0xffu];
-                const float4 xj = W.pos[id >> 8];
+                const float3 xj = W.pos[id >> 8];
                 const float wx = c.px - xj.x, wy = c.py - xj.y, wz = c.pz - xj.z;
                 const float A = fmaf(wx, wx, fmaf(wy, wy, fmaf(wz, wz, c.rho * c.rho)));
                 const float C = 2.0f * fmaf(wx, c.ax, fmaf(wy, c.ay, wz * c.az));
@@ -517,14 +553,13 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
             const uint64_t bal = __ballot(mv);
             const int cnt = __popcll(bal);
             if (mv) {
+                const float3 x = W.pos[i];
                 Coef c;
-                circle(ux, uy, uz, xax, xay, xaz, cx[h], cy[h], cz[h], c.px, c.py, c.pz, c.ax, c.ay, c.az, c.bx, c.by,
-                       c.bz);
+                circle(ux, uy, uz, xax, xay, xaz, x.x, x.y, x.z, c.px, c.py, c.pz, c.ax, c.ay, c.az, c.bx, c.by, c.bz);
                 c.rho = __builtin_amdgcn_sqrtf(fmaf(c.ax, c.ax, fmaf(c.ay, c.ay, c.az * c.az)));
-                c.zz = fmaf(ux, cx[h] - xax, fmaf(uy, cy[h] - xay, uz * (cz[h] - xaz)));
-                const bool inside = c.px - c.rho >= edge && c.py - c.rho >= edge && c.pz - c.rho >= edge &&
-                                    c.px + c.rho <= g.mx - edge && c.py + c.rho <= g.my - edge &&
-                                    c.pz + c.rho <= g.mz - edge;
+                c.zz = fmaf(ux, x.x - xax, fmaf(uy, x.y - xay, uz * (x.z - xaz)));
+                const bool inside = c.px - c.rho >= g.in_lo && c.py - c.rho >= g.in_lo && c.pz - c.rho >= g.in_lo &&
+                                    c.px + c.rho <= g.in_x && c.py + c.rho <= g.in_y && c.pz + c.rho <= g.in_z;
                 c.tof = L.tof[i] | (inside ? kInside : 0u);
                 const int slot = lanes_below(bal);
                 W.coef[slot] = c;
@@ -581,6 +616,22 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
                         if (q0 + a < cnt)
 #pragma unroll
                             for (int jj = 0; jj < NJ; ++jj) e[j0 + jj] += v[a * NJ + jj];
+                }
+            }
+            // fixed atoms: cylinder coordinates about the axis (radius +inf for the others, so that
+            // no pair with them passes the closest-approach test)
+            float zj[2], rj[2];
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+                const int jj = lane + kWave * h2;
+                zj[h2] = 0.0f;
+                rj[h2] = INFINITY;
+                if (jj < n && !mask_has_lane(mask, h2, lane)) {
+                    const float3 x = W.pos[jj];
+                    const float vx = x.x - xax, vy = x.y - xay, vz = x.z - xaz;
+                    zj[h2] = fmaf(ux, vx, fmaf(uy, vy, uz * vz));
+                    const float ox = fmaf(-zj[h2], ux, vx), oy = fmaf(-zj[h2], uy, vy), oz = fmaf(-zj[h2], uz, vz);
+                    rj[h2] = __builtin_amdgcn_sqrtf(fmaf(ox, ox, fmaf(oy, oy, oz * oz)));
                 }
             }
             // (moving, fixed) clash pairs that can come within the cut-off somewhere on the circle
@@ -647,19 +698,31 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
         for (int h = 0; h < 2; ++h) {
             const int i = lane + kWave * h;
             if (i < n && mask_has(mask, i)) {
+                const float3 x = W.pos[i];
                 float px, py, pz, ax, ay, az, bx, by, bz;
-                circle(ux, uy, uz, xax, xay, xaz, cx[h], cy[h], cz[h], px, py, pz, ax, ay, az, bx, by, bz);
-                cx[h] = fmaf(ax, cb, fmaf(bx, sb, px));
-                cy[h] = fmaf(ay, cb, fmaf(by, sb, py));
-                cz[h] = fmaf(az, cb, fmaf(bz, sb, pz));
+                circle(ux, uy, uz, xax, xay, xaz, x.x, x.y, x.z, px, py, pz, ax, ay, az, bx, by, bz);
+                W.pos[i] = make_float3(fmaf(ax, cb, fmaf(bx, sb, px)), fmaf(ay, cb, fmaf(by, sb, py)),
+                                       fmaf(az, cb, fmaf(bz, sb, pz)));
             }
         }
+        wave_sync();
         if (lane == k) {  // total turn of torsion k over the passes, modulo S
             my_step += sbest;
             my_step -= my_step >= s.S ? s.S : 0;
         }
     }
-    if (Emax > 16.0f * fmaxf(1.0f, fabsf(E))) E = direct_score<BOUNDARY, LAYOUT>(g, rs, s, L, cx, cy, cz);
+    if (Emax > 16.0f * fmaxf(1.0f, fabsf(E))) {
+        float cx[2], cy[2], cz[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = lane + kWave * h;
+            const float3 x = i < n ? W.pos[i] : make_float3(0.0f, 0.0f, 0.0f);
+            cx[h] = x.x;
+            cy[h] = x.y;
+            cz[h] = x.z;
+        }
+        E = direct_score<BOUNDARY, LAYOUT>(g, rs, s, L, cx, cy, cz);
+    }
     return E;
 }
 
@@ -850,7 +913,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         __syncthreads();
         const int64_t item = item_s;
         if (item >= A.n_items) break;
-        const int slot = (int)(item / A.bpl), batch = (int)(item - (int64_t)slot * A.bpl);
+        // items run batch-major: batch b of every ligand (in cost order) before batch b + 1
+        const int batch = (int)(item / A.n_lig), slot = (int)(item - (int64_t)batch * A.n_lig);
         const int lig = (int)(uint32_t)A.order[slot];
         load_ligand(L, A.pk, lig, A.g, tid, blockDim.x);
         __syncthreads();
@@ -859,7 +923,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             uint64_t wbest = ~0ull;
             const int p0 = batch * A.P, p1 = min(p0 + A.P, A.s.top ? A.s.top : A.s.QT);
             for (int idx = p0 + w; idx < p1; idx += A.nw) {
-                const int p = A.s.top ? (int)A.sel[(size_t)lig * A.s.top + idx] : idx;
+                // the full start set is enumerated translation-major (idx = it * n_quat + iq)
+                const int p = A.s.top ? (int)A.sel[(size_t)lig * A.s.top + idx]
+                                      : (idx % A.s.n_quat) * A.s.n_trans + idx / A.s.n_quat;
                 int step = 0;
                 const float E = run_start<APL, BOUNDARY, LAYOUT>(A.g, rs, A.s, L, W, p, clash_ref, cs, sn, step);
                 const uint64_t key = ((uint64_t)float_to_ordered(E) << 32) | (uint32_t)p;
@@ -1224,9 +1290,8 @@ static GridC make_grid(const dock_grid_desc *d, const float *G) {
     g.frow = (float)g.row;
     g.fplane = (float)g.plane;
     g.geo = Xy4Geom::of(d->nx, d->ny, d->nz);
-    g.ky = 64.0f * (float)g.geo.nxp - 32.0f;
-    g.kz = 64.0f * (float)g.geo.nxp * (float)g.geo.nby - 64.0f;
-    g.dz_odd = 64u * g.geo.nxp * g.geo.nby - 32u;
+    g.ky = 64u * g.geo.nxp - 32u;
+    g.kz = 64u * g.geo.nxp * g.geo.nby - 64u;
     g.inv_h = 1.0f / d->spacing;
     g.ox_h = d->origin[0] / d->spacing;
     g.oy_h = d->origin[1] / d->spacing;
@@ -1234,6 +1299,10 @@ static GridC make_grid(const dock_grid_desc *d, const float *G) {
     g.mx = (float)(d->nx - 1);
     g.my = (float)(d->ny - 1);
     g.mz = (float)(d->nz - 1);
+    g.in_lo = kEdge;
+    g.in_x = g.mx - kEdge;
+    g.in_y = g.my - kEdge;
+    g.in_z = g.mz - kEdge;
     g.cx = (float)(d->nx - 2);
     g.cy = (float)(d->ny - 2);
     g.cz = (float)(d->nz - 2);

@@ -108,6 +108,12 @@ def test_grid_desc_validation():
     odd = dict(nx=255, ny=255, nz=255, n_types=1)  # < 2^24 nodes, but 128^3 bricks = 2^28 bytes
     assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, layout=0, **odd)), ctypes.byref(out)) == 0
     assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, layout=1, **odd)), ctypes.byref(out)) == -2
+    # xy4 record offsets use 24-bit multiplies: (nx rounded up to even) * ceil(ny / 2) <= 2^18
+    wide = dict(nx=2048, ny=1024, nz=2, n_types=1)  # 2048 * 512 = 2^20
+    assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, layout=0, **wide)), ctypes.byref(out)) == 0
+    assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, layout=1, **wide)), ctypes.byref(out)) == -2
+    edge = dict(nx=1024, ny=512, nz=4, n_types=1)  # 1024 * 256 = 2^18
+    assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, layout=1, **edge)), ctypes.byref(out)) == 0
     big = dict(nx=200, ny=200, nz=200, n_types=17)  # 8e6 nodes x 17 types x 16 B > 2^31
     assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, layout=0, **big)), ctypes.byref(out)) == 0
     assert lib.dock_grid_bytes(ctypes.byref(_desc(dock, layout=1, **big)), ctypes.byref(out)) == -2

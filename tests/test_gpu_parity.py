@@ -55,24 +55,24 @@ def test_xy4_records_hold_the_wrapped_neighbours(P):
     rec = P.DevicePocket(pocket, layout=1).records()
     # dims of the [t][z][y][x] view: x is 3, y is 2
     lin_y = torch.roll(lin, -1, dims=2)
+    d_x = torch.roll(lin, -1, dims=3) - lin  # FP32 differences
     assert torch.equal(rec[..., 0], lin)
-    assert torch.equal(rec[..., 1], torch.roll(lin, -1, dims=3) - lin)  # FP32 differences
-    assert torch.equal(rec[..., 2], lin_y)
-    assert torch.equal(rec[..., 3], torch.roll(lin_y, -1, dims=3) - lin_y)
+    assert torch.equal(rec[..., 1], d_x)
+    assert torch.equal(rec[..., 2], lin_y - lin)
+    assert torch.equal(rec[..., 3], (torch.roll(lin_y, -1, dims=3) - lin_y) - d_x)
     # storage order: [t][z/2][y/2][x][z&1][y&1] records of 16 bytes
     dp = P.DevicePocket(pocket, layout=1)
     raw = dp.grids.view(4, 14, 18, 40, 2, 2, 4)
     # record (x 15, y 10, z 7): z/2 = 3, y/2 = 5, z&1 = 1, y&1 = 0
-    assert torch.equal(raw[1, 3, 5, 15, 1, 0],
-                       torch.stack([lin[1, 7, 10, 15], lin[1, 7, 10, 16] - lin[1, 7, 10, 15], lin[1, 7, 11, 15],
-                                    lin[1, 7, 11, 16] - lin[1, 7, 11, 15]]))
+    g00, g10, g01, g11 = lin[1, 7, 10, 15], lin[1, 7, 10, 16], lin[1, 7, 11, 15], lin[1, 7, 11, 16]
+    assert torch.equal(raw[1, 3, 5, 15, 1, 0], torch.stack([g00, g10 - g00, g01 - g00, (g11 - g01) - (g10 - g00)]))
     # odd dimensions: padding records are zero
     odd = I.make_pocket((13, 7, 5), 2, pocket_id=4)
     say("xy4 records of a 13x7x5 grid (padded to 14x8x6)")
     o_lin = P.DevicePocket(odd, layout=0).view()
     o_dp = P.DevicePocket(odd, layout=1)
     o_rec = o_dp.records()
-    assert torch.equal(o_rec[..., 0], o_lin) and torch.equal(o_rec[..., 2], torch.roll(o_lin, -1, dims=2))
+    assert torch.equal(o_rec[..., 0], o_lin) and torch.equal(o_rec[..., 2], torch.roll(o_lin, -1, dims=2) - o_lin)
     assert o_dp.grids.numel() == 2 * 14 * 4 * 3 * 16
     full = o_dp.grids.view(2, 3, 4, 14, 2, 2, 4).permute(0, 1, 4, 2, 5, 3, 6).reshape(2, 6, 8, 14, 4)
     assert torch.all(full[:, 5:] == 0) and torch.all(full[:, :, 7:] == 0) and torch.all(full[:, :, :, 13:] == 0)
