@@ -218,7 +218,18 @@ def rodrigues(u, th: float, v) -> np.ndarray:
     return out
 
 
+def _check(ligs, srch, lig, start):
+    """Ligand and start indices must lie in the library and the start set (the C code trusts them)."""
+    lig, start = np.atleast_1d(lig), np.atleast_1d(start)
+    if lig.size and (lig.min() < 0 or lig.max() >= ligs.n_lig):
+        raise ValueError("ligand index outside the library")
+    qt = len(srch.quat) * len(srch.trans)
+    if start.size and (start.min() < 0 or start.max() >= qt):
+        raise ValueError(f"start index outside the {qt} starts")
+
+
 def pose_coords(ligs, srch, l: int, p: int, steps=(), upto: int = MAX_TORS) -> np.ndarray:
+    _check(ligs, srch, l, p)
     lib, s = library(ligs), search(srch)
     st = np.zeros(MAX_TORS, np.int32)
     st[:len(steps)] = steps
@@ -270,6 +281,7 @@ def dock(pocket, G, ligs, srch, sel=None, per_start: bool = False, periodic: boo
 def greedy_starts(pocket, G, ligs, srch, lig, start, periodic: bool = False) -> dict:
     lig = np.ascontiguousarray(lig, dtype=np.int64)
     start = np.ascontiguousarray(start, dtype=np.int32)
+    _check(ligs, srch, lig, start)
     n = len(lig)
     lib, s = library(ligs), search(srch)
     G = np.ascontiguousarray(G, dtype=np.float32)
@@ -284,6 +296,7 @@ def greedy_starts(pocket, G, ligs, srch, lig, start, periodic: bool = False) -> 
 def score_poses(pocket, G, ligs, srch, lig, start, steps, periodic: bool = False) -> np.ndarray:
     lig = np.ascontiguousarray(lig, dtype=np.int64)
     start = np.ascontiguousarray(start, dtype=np.int32)
+    _check(ligs, srch, lig, start)
     st = np.zeros((len(lig), MAX_TORS), np.int32)
     steps = np.asarray(steps, dtype=np.int32).reshape(len(lig), -1)
     st[:, :steps.shape[1]] = steps
@@ -298,6 +311,7 @@ def score_poses(pocket, G, ligs, srch, lig, start, steps, periodic: bool = False
 def replay(pocket, G, ligs, srch, lig, start, steps, periodic: bool = False) -> dict:
     lig = np.ascontiguousarray(lig, dtype=np.int64)
     start = np.ascontiguousarray(start, dtype=np.int32)
+    _check(ligs, srch, lig, start)
     st = np.zeros((len(lig), MAX_TORS), np.int32)
     steps = np.asarray(steps, dtype=np.int32).reshape(len(lig), -1)
     st[:, :steps.shape[1]] = steps
@@ -337,6 +351,7 @@ def filter_rescore(pocket, ligs, srch, l: int, start, steps, rmsd_min: float) ->
     lib, s, pot = library(ligs), search(srch), potential(pocket)
     xyz, t = _prot(pocket)
     start = np.ascontiguousarray(start, dtype=np.int32)
+    _check(ligs, srch, l, start[start >= 0])  # start < 0 marks an absent pose
     n = len(start)
     st = np.zeros((n, MAX_TORS), np.int32)
     st[:, :np.shape(steps)[1]] = steps
