@@ -493,6 +493,75 @@ def read_peak(mib=2, blk=2048, reps=64):
     return best
 
 
+def surrogate_roofline(args):
+    """MFMA throughput of the pre-filter network: the forward pass at the prediction chunk size and
+    at a large batch, and one training step (forward, backward, Adam) at the training batch, each
+    timed with HIP events (best of three after a warm-up) against the dense BF16 peak."""
+    import numpy as np
+    import torch
+
+    from paper_2304_09953_amd import inputs as I
+    from paper_2304_09953_amd import surrogate as SG
+    peak = 2.5e15
+    d_in, h1, h2 = 512, 1024, 1024
+    model = SG.Model(I.mlp_init(d_in, h1, h2))
+    fwd_flop = 2.0 * (d_in * h1 + h1 * h2 + h2)  # per row
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def best_of(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = ev(), ev()
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e-3)
+        return best
+
+    rows = []
+    for batch in (65536, 1 << 20):
+        x = (torch.randn((batch, d_in), generator=gen, device="cuda") * 0.5).to(torch.bfloat16).view(torch.int16)
+        y = torch.empty(batch, dtype=torch.float32, device="cuda")
+        t = best_of(lambda: model.forward(x, y))
+        rows.append({"pass": "forward", "batch": batch, "seconds": t, "tflops": fwd_flop * batch / t / 1e12,
+                     "frac": fwd_flop * batch / t / peak})
+        log(f"forward batch {batch}: {t * 1e3:.2f} ms, {fwd_flop * batch / t / 1e12:.1f} TFLOP/s")
+        del x, y
+    batch = 1024
+    x = (torch.randn((batch, d_in), generator=gen, device="cuda") * 0.5).to(torch.bfloat16).view(torch.int16)
+    tgt = torch.randn(batch, generator=gen, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+
+    def step():
+        model.backward(x, tgt, loss)
+        model.adam(1e-4)
+    t = best_of(step)
+    # forward, then the weight and input gradients of the two hidden layers (the input layer needs no
+    # input gradient): 3 x forward minus one d_in x h1 product
+    step_flop = batch * (3 * fwd_flop - 2.0 * d_in * h1)
+    rows.append({"pass": "training step", "batch": batch, "seconds": t, "tflops": step_flop / t / 1e12,
+                 "frac": step_flop / t / peak})
+    log(f"training step batch {batch}: {t * 1e3:.3f} ms, {step_flop / t / 1e12:.1f} TFLOP/s")
+    # reference point: the library BF16 GEMM behind torch.matmul on the first layer's product
+    # (no bias, no activation) at the large batch
+    xa = torch.randn((1 << 20, d_in), generator=gen, device="cuda").to(torch.bfloat16)
+    wa = torch.randn((h1, d_in), generator=gen, device="cuda").to(torch.bfloat16)
+    out = torch.empty((1 << 20, h1), dtype=torch.bfloat16, device="cuda")
+    t = best_of(lambda: torch.matmul(xa, wa.t(), out=out))
+    lib_flop = 2.0 * (1 << 20) * d_in * h1
+    rows.append({"pass": "library GEMM (torch.matmul, first layer product only)", "batch": 1 << 20, "seconds": t,
+                 "tflops": lib_flop / t / 1e12, "frac": lib_flop / t / peak})
+    log(f"torch.matmul {1 << 20} x {d_in} x {h1}: {t * 1e3:.2f} ms, {lib_flop / t / 1e12:.1f} TFLOP/s")
+    print(json.dumps({"metric": "pre-filter network MFMA throughput", "unit": "TFLOP/s",
+                      "peak": {"bf16_dense_tflops": peak / 1e12},
+                      "config": {"network": f"{d_in}-{h1}-{h2}-1, BF16 weights and activations, FP32 accumulation"},
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -538,6 +607,8 @@ def main():
     ap.add_argument("--pf-margin", type=float, default=0.02, help="added to the target when calibrating")
     ap.add_argument("--pf-epochs", type=int, default=20, help="most epochs per member (early stopping)")
     ap.add_argument("--pf-members", type=int, default=4, help="networks in the ensemble")
+    ap.add_argument("--surrogate-roofline", action="store_true",
+                    help="MFMA throughput of the pre-filter network's forward pass and training step")
     args = ap.parse_args()
     if args.summarize_counters:
         return summarize_counters(args.summarize_counters)
@@ -576,6 +647,8 @@ def main():
         return knob_tuning(args)
     if args.prefilter:
         return prefilter_bench(args)
+    if args.surrogate_roofline:
+        return surrogate_roofline(args)
     W = I.workload("pocket96-lib100k")
     n_lig = args.n_lig or W.n_lig
     log(f"generating {n_lig} ligands")

@@ -65,7 +65,8 @@ def test_invalid_ligands_get_zero_features(env):
     assert np.allclose(F[ok], S.features(ligs.subset(ok)), rtol=2e-7, atol=1e-7)
 
 
-@pytest.mark.parametrize("dims,batch", [((64, 64, 64), 40), ((512, 1024, 1024), 1024), ((128, 192, 64), 97)])
+@pytest.mark.parametrize("dims,batch", [((64, 64, 64), 40), ((512, 1024, 1024), 1024), ((128, 192, 64), 97),
+                                        ((512, 1024, 1024), 5000)])
 def test_forward_matches_bf16_mirror(env, dims, batch):
     P, SG = env
     d, h1, h2 = dims
@@ -80,6 +81,24 @@ def test_forward_matches_bf16_mirror(env, dims, batch):
     y_ref, _ = S.forward(S.Params(d, h1, h2), init.astype(np.float64), X)
     say(f"forward rel err {_rel(y, y_ref):.3g}")
     assert _rel(y, y_ref) < 2e-3
+
+
+@pytest.mark.parametrize("dims", [(512, 1024, 1024), (128, 256, 128)])
+def test_large_batches_equal_small_ones(env, dims):
+    # every row's output depends on that row alone and takes the same MFMA sequence over K whatever
+    # the batch, so a large batch and its chunks agree bit for bit
+    P, SG = env
+    d, h1, h2 = dims
+    rng = np.random.default_rng(11)
+    init = I.mlp_init(d, h1, h2, seed=3)
+    init[d * h1:d * h1 + h1] = rng.normal(size=h1) * 0.1
+    m = SG.Model(init, d, h1, h2)
+    n = 9000  # 35 row blocks of 256 and a ragged tail
+    xb = torch.as_tensor(S.bf16_bits(rng.normal(size=(n, d)).astype(np.float32)).view(np.int16)).cuda()
+    say(f"forward {dims}: batch {n} against chunks of 1500")
+    big = m.forward(xb)
+    small = torch.cat([m.forward(xb[s:s + 1500]) for s in range(0, n, 1500)])
+    assert torch.equal(big, small)
 
 
 def test_backward_and_adam_match_oracle(env):
