@@ -283,6 +283,27 @@ def test_screen_edge_cases(P):
         assert g["poses"] == oracle.pose_count(ligs.n_rot, st, srch.n_starts, S)
 
 
+def test_32_atom_types(P):
+    # the largest type table: grids of 32 types in both layouts and a screen whose ligands use them all
+    pocket = I.make_pocket((30, 28, 26), 32, pocket_id=12)
+    G = oracle.build_grids(pocket)
+    ligs = I.make_ligands(24, I.DIST_DRUGLIKE, 32, stream="test")
+    t_used = np.unique(np.concatenate([ligs.ligand(i)[1] for i in range(ligs.n_lig)]))
+    srch = I.make_search(6, 2, 32, 2.0, pocket.center)
+    for layout in (0, 1):
+        say(f"32-type grids 30x28x26, layout {layout}, and a 24-ligand screen (types used: {len(t_used)})")
+        dp = P.DevicePocket(pocket, layout=layout)
+        g = dp.view().cpu().numpy()
+        err = np.abs(g.astype(np.float64) - G) / np.maximum(1.0, np.abs(G))
+        assert err.max() <= 1e-6
+        r = _screen(P, dp, ligs, srch)
+        sel = np.arange(ligs.n_lig)
+        check_exact_and_valid(pocket, G, ligs, srch, sel, r["score"], r["start"], r["steps"])
+        orc = oracle.dock(pocket, G, ligs, srch, per_start=True)
+        check_optimal(pocket, G, ligs, srch, sel, r["score"], r["start"], orc)
+    assert t_used.max() >= 16  # the upper half of the table is exercised
+
+
 def test_screen_is_deterministic_and_tuning_invariant(P, p48):
     W, pocket, dp, G, ligs = p48
     sub = ligs.subset(np.arange(0, 100, 9))
