@@ -55,7 +55,8 @@ class SearchC(ctypes.Structure):
     _fields_ = [("n_quat", ctypes.c_int32), ("quat", ctypes.POINTER(ctypes.c_float)),
                 ("n_trans", ctypes.c_int32), ("trans", ctypes.POINTER(ctypes.c_float)),
                 ("n_steps", ctypes.c_int32), ("clash_cut", ctypes.c_double), ("clash_w", ctypes.c_double),
-                ("sweep_top", ctypes.c_int32), ("passes", ctypes.c_int32)]
+                ("sweep_top", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("init_steps", ctypes.POINTER(ctypes.c_int32))]
 
 
 _lib = None
@@ -122,9 +123,18 @@ def library(ligs) -> _Keep:
 def search(s) -> _Keep:
     q = np.ascontiguousarray(s.quat, dtype=np.float32)
     t = np.ascontiguousarray(s.trans, dtype=np.float32)
+    R = int(getattr(s, "restarts", 0))
+    init = np.zeros((max(R, 1), MAX_TORS), np.int32)
+    if R:
+        if int(getattr(s, "sweep_top", 0)):
+            raise ValueError("torsion restarts are not combined with sweep_top")
+        given = np.asarray(s.init_steps, dtype=np.int32).reshape(R, -1)
+        if given.min() < 0 or given.max() >= s.n_steps:
+            raise ValueError("initial turns must lie in [0, n_steps)")
+        init[:, :given.shape[1]] = given
     c = SearchC(len(q), _p(q, _F32), len(t), _p(t, _F32), int(s.n_steps), float(s.clash_cut), float(s.clash_w),
-                int(getattr(s, "sweep_top", 0)), int(getattr(s, "passes", 1)))
-    return _Keep(c, q, t)
+                int(getattr(s, "sweep_top", 0)), int(getattr(s, "passes", 1)), R, _p(init, _I32))
+    return _Keep(c, q, t, init)
 
 
 # ------------------------------------------------------------------------------------------------
@@ -223,9 +233,9 @@ def _check(ligs, srch, lig, start):
     lig, start = np.atleast_1d(lig), np.atleast_1d(start)
     if lig.size and (lig.min() < 0 or lig.max() >= ligs.n_lig):
         raise ValueError("ligand index outside the library")
-    qt = len(srch.quat) * len(srch.trans)
+    qt = len(srch.quat) * len(srch.trans) * (1 + int(getattr(srch, "restarts", 0)))
     if start.size and (start.min() < 0 or start.max() >= qt):
-        raise ValueError(f"start index outside the {qt} starts")
+        raise ValueError(f"start index outside the {qt} searched starts")
 
 
 def pose_coords(ligs, srch, l: int, p: int, steps=(), upto: int = MAX_TORS) -> np.ndarray:
@@ -260,7 +270,7 @@ def dock(pocket, G, ligs, srch, sel=None, per_start: bool = False, periodic: boo
     lib, s = library(ligs), search(srch)
     G = np.ascontiguousarray(G, dtype=np.float32)
     n = len(sel)
-    QT = srch.n_starts
+    QT = srch.n_searched
     best = np.zeros(n, np.float64)
     bp = np.zeros(n, np.int32)
     bs = np.zeros((n, MAX_TORS), np.int32)

@@ -388,7 +388,15 @@ typedef struct {
     double clash_cut, clash_w;
     int32_t sweep_top;  /* 0: every start gets the torsion sweeps; K > 0: only the K best rigid starts */
     int32_t passes;     /* greedy passes over the torsions (values below 1 count as 1) */
+    int32_t restarts;   /* R: torsion restarts per rigid start (not combined with sweep_top) */
+    const int32_t *init_steps; /* [R][16] initial turn of torsion k of restart r, in [0, S) */
 } or_search;
+
+/* Searched starts: (1 + R) Q T; start e is restart e / (Q T) of rigid start e mod (Q T). */
+static int64_t or_n_starts(const or_search *s)
+{
+    return (int64_t)s->n_quat * s->n_trans * (1 + (s->restarts > 0 ? s->restarts : 0));
+}
 
 /*
  * Score of conformer X: the sum over atoms of the interpolated grid value of the
@@ -406,9 +414,11 @@ double or_score(const or_lig *L, const double X[][3], const or_frame *f, const f
     return e;
 }
 
-/* Rigid start p = iq * n_trans + it: X = R(q_iq) Xref + t_it. */
+/* Rigid start p = iq * n_trans + it: X = R(q_iq) Xref + t_it (p is taken modulo Q T, so a
+   searched start e gives its rigid start). */
 void or_place(const or_lig *L, const or_search *s, int p, double X[][3])
 {
+    p %= s->n_quat * s->n_trans;
     int iq = p / s->n_trans, it = p % s->n_trans;
     double q[4] = {s->quat[4 * iq], s->quat[4 * iq + 1], s->quat[4 * iq + 2], s->quat[4 * iq + 3]};
     double Rm[9];
@@ -436,13 +446,31 @@ void or_turn(const or_lig *L, const or_search *s, int k, int step, const double 
 }
 
 /*
- * Greedy search from rigid start p: for each torsion in sweep order, score the
- * conformer turned by every step, keep the lowest (ties to the lowest step), and
- * move on with that conformer; the whole pass over the torsions is made s->passes
- * times.  Returns the final score.  steps[k] receives torsion k's total turn, the sum
- * of its chosen steps over the passes modulo S (a turn changes only its own torsion
- * angle, so the final conformer is the reference one with each torsion turned once by
- * its total); min_gap (may be NULL) the smallest relative decision gap met,
+ * The conformer searched start e begins from: rigid start e mod (Q T), then, for restart
+ * r = e / (Q T) >= 1, each torsion k turned by init_steps[r - 1][k] in sweep order (a zero turn
+ * leaves the torsion as it is).  steps[k] receives that initial turn (0 for r = 0).
+ */
+static void or_start(const or_lig *L, const or_search *s, int e, double X[][3], int steps[])
+{
+    double Y[OR_MAX_ATOMS][3];
+    const int r = e / (s->n_quat * s->n_trans);
+    or_place(L, s, e, X);
+    for (int k = 0; k < L->B; ++k) {
+        steps[k] = r > 0 ? s->init_steps[(r - 1) * OR_MAX_TORS + k] : 0;
+        if (steps[k] == 0) continue;  /* no turn: the torsion is left as it is */
+        or_turn(L, s, k, steps[k], (const double(*)[3])X, Y);
+        memcpy(X, Y, sizeof(double) * 3 * L->n);
+    }
+}
+
+/*
+ * Greedy search from searched start p (a rigid start, or a torsion restart of one: or_start):
+ * for each torsion in sweep order, score the conformer turned by every step, keep the lowest
+ * (ties to the lowest step), and move on with that conformer; the whole pass over the torsions
+ * is made s->passes times.  Returns the final score.  steps[k] receives torsion k's total turn,
+ * its initial turn plus its chosen steps over the passes, modulo S (a turn changes only its own
+ * torsion angle, so the final conformer is the rigid start's with each torsion turned once by its
+ * total); min_gap (may be NULL) the smallest relative decision gap met,
  * (second-lowest - lowest) / max(1, |lowest|), +inf if there was no decision.
  */
 double or_greedy(const or_lig *L, const or_frame *f, const float *G, const or_search *s, int p, int steps[],
@@ -451,8 +479,7 @@ double or_greedy(const or_lig *L, const or_frame *f, const float *G, const or_se
     double X[OR_MAX_ATOMS][3], Y[OR_MAX_ATOMS][3], Best[OR_MAX_ATOMS][3];
     double gap = INFINITY;
     const int passes = s->passes > 1 ? s->passes : 1;
-    or_place(L, s, p, X);
-    for (int k = 0; k < L->B; ++k) steps[k] = 0;
+    or_start(L, s, p, X, steps);
     for (int pass = 0; pass < passes; ++pass)
     for (int k = 0; k < L->B; ++k) {
         double e1 = INFINITY, e2 = INFINITY;
@@ -472,7 +499,8 @@ double or_greedy(const or_lig *L, const or_frame *f, const float *G, const or_se
     return or_score(L, (const double(*)[3])X, f, G, s);
 }
 
-/* Score of the explicit pose (start p, steps[k] for each torsion in sweep order). */
+/* Score of the explicit pose (start p, steps[k] for each torsion in sweep order: the total turns
+   from the rigid start p mod Q T). */
 double or_pose_score(const or_lig *L, const or_frame *f, const float *G, const or_search *s, int p,
                      const int32_t steps[])
 {
@@ -555,22 +583,24 @@ static int or_keyed_cmp(const void *a, const void *b)
 /*
  * Docks the selected ligands.  The greedy search is run from every rigid start (the
  * multiple restarts), or, with s->sweep_top = K in [1, Q*T), only from the K starts
- * whose rigid pose scores lowest (ties to the lower start); the ligand's result is its
- * best searched start, ties to the lowest start index.  Ligands with a non-OK status
- * get +inf and start -1.  Optional per-start outputs: finals [n_sel][Q*T] (+inf for
- * starts not searched), start_steps [n_sel][Q*T][16], start_gap [n_sel][Q*T].
+ * whose rigid pose scores lowest (ties to the lower start); with s->restarts = R > 0 also
+ * from R torsion restarts of every rigid start (or_start), (1 + R) Q T searched starts.
+ * The ligand's result is its best searched start, ties to the lowest start index.
+ * Ligands with a non-OK status get +inf and start -1.  Optional per-start outputs: finals
+ * [n_sel][N] (+inf for starts not searched), start_steps [n_sel][N][16], start_gap
+ * [n_sel][N], N the number of searched starts.
  */
 int or_dock(const or_frame *f, const float *G, const or_library *lib, const or_search *s, int32_t n_sel,
             const int64_t *sel, double *best, int32_t *best_p, int32_t *best_steps, int32_t *status,
             double *finals, int32_t *start_steps, double *start_gap)
 {
     or_lig *Ls = load_selection(lib, n_sel, sel);
-    int64_t QT = (int64_t)s->n_quat * s->n_trans;
+    int64_t QT = or_n_starts(s);  /* searched starts, restarts included */
     size_t cells = (size_t)(n_sel * QT > 0 ? n_sel * QT : 1);
     double *fin = (double *)malloc(sizeof(double) * cells);
     int32_t *stp = (int32_t *)malloc(sizeof(int32_t) * OR_MAX_TORS * cells);
     uint8_t *searched = (uint8_t *)malloc(cells);
-    const int top = s->sweep_top > 0 && s->sweep_top < QT;
+    const int top = s->restarts <= 0 && s->sweep_top > 0 && s->sweep_top < QT;
     memset(searched, top ? 0 : 1, cells);
     if (top) {
         /* rigid scores of every start, then the K lowest per ligand */
@@ -667,9 +697,10 @@ int or_score_poses(const or_frame *f, const float *G, const or_library *lib, con
 }
 
 /*
- * Follows a given path (start, steps) and, at every torsion, reports the score
- * of the given step and the lowest score over all steps from the same conformer;
- * used to check that each decision of another implementation is a (near-)argmin.
+ * Follows a given path (searched start, total turns) and, at every torsion, reports the score
+ * of the given step (the total less the start's initial turn) and the lowest score over all
+ * steps from the same conformer; used to check that each decision of another implementation
+ * is a (near-)argmin.  One pass.
  */
 int or_replay(const or_frame *f, const float *G, const or_library *lib, const or_search *s, int64_t n,
               const int64_t *lig, const int32_t *start, const int32_t *steps, double *e_given, double *e_min,
@@ -684,10 +715,12 @@ int or_replay(const or_frame *f, const float *G, const or_library *lib, const or
             or_ligand(lib, lig[w], L);
             for (int k = 0; k < OR_MAX_TORS; ++k) { e_given[w * OR_MAX_TORS + k] = NAN; e_min[w * OR_MAX_TORS + k] = NAN; }
             if (L->status != OR_LIG_OK) { final[w] = INFINITY; continue; }
-            or_place(L, s, start[w], X);
+            int init[OR_MAX_TORS];
+            or_start(L, s, start[w], X, init);
             for (int k = 0; k < L->B; ++k) {
                 double emin = INFINITY, eg = NAN;
-                int sg = steps[w * OR_MAX_TORS + k];
+                /* the given steps are total turns; the decision is the turn on top of the start's */
+                int sg = ((steps[w * OR_MAX_TORS + k] - init[k]) % s->n_steps + s->n_steps) % s->n_steps;
                 for (int st = 0; st < s->n_steps; ++st) {
                     or_turn(L, s, k, st, (const double(*)[3])X, Y);
                     double e = or_score(L, (const double(*)[3])Y, f, G, s);

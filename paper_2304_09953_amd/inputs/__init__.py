@@ -256,10 +256,17 @@ class Search:
     clash_w: float = 10.0
     sweep_top: int = 0    # 0: every start gets the torsion sweeps; K: only the K best rigid starts
     passes: int = 1       # greedy passes over the torsions
+    restarts: int = 0     # R torsion restarts per rigid start (not combined with sweep_top)
+    init_steps: np.ndarray | None = None  # int32 [R][16]: initial turn of each torsion, in [0, n_steps)
 
     @property
     def n_starts(self) -> int:
         return len(self.quat) * len(self.trans)
+
+    @property
+    def n_searched(self) -> int:
+        """Searched starts: every rigid start and its torsion restarts, (1 + R) Q T."""
+        return self.n_starts * (1 + self.restarts)
 
 
 def quaternions(n: int) -> np.ndarray:
@@ -273,6 +280,12 @@ def translations(n: int, radius: float, center, seed: int = BASE_SEED) -> np.nda
     c = np.ascontiguousarray(center, dtype=np.float64)
     _load().gen_translations(seed, STREAMS["search"], n, radius, _ptr(c, ctypes.c_double), _ptr(t, ctypes.c_float))
     return t
+
+
+def restart_steps(n_restarts: int, n_steps: int, seed: int = BASE_SEED) -> np.ndarray:
+    """Seeded initial torsion turns of the restarts: int32 [n_restarts][16], uniform in [0, n_steps)."""
+    rng = np.random.default_rng([seed, 0x7e57a7, n_steps])
+    return rng.integers(0, n_steps, (n_restarts, 16)).astype(np.int32)
 
 
 def make_search(n_quat: int, n_trans: int, n_steps: int, radius: float, center) -> Search:
@@ -332,4 +345,4 @@ def mlp_init(d_in: int = 512, h1: int = 1024, h2: int = 1024, seed: int = BASE_S
 def search_for(pocket: Pocket, base: Search, radius: float = 4.0) -> Search:
     """The same search centred on another pocket (translations follow the pocket centre)."""
     return Search(base.quat, translations(len(base.trans), radius, pocket.center), base.n_steps,
-                  base.clash_cut, base.clash_w, base.sweep_top, base.passes)
+                  base.clash_cut, base.clash_w, base.sweep_top, base.passes, base.restarts, base.init_steps)
