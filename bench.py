@@ -406,10 +406,13 @@ def budget_curve(args):
     ligs = W.ligands(n_lig=n_lig)
     dp = P.DevicePocket(W.pockets[0])
     lib = P.DeviceLibrary(ligs)
-    variants = [(0, 1), (0, 2), (1024, 1), (256, 1), (256, 2), (64, 1), (64, 2), (16, 1), (4, 1), (1, 1)]
+    # (sweep_top, passes, torsion restarts per rigid start)
+    variants = [(0, 1, 0), (0, 2, 0), (0, 1, 1), (0, 1, 3), (1024, 1, 0), (256, 1, 0), (256, 2, 0), (64, 1, 0),
+                (64, 2, 0), (16, 1, 0), (4, 1, 0), (1, 1, 0)]
     rows, ref = [], None
-    for top, passes in variants:
-        srch = dataclasses.replace(W.search, sweep_top=top, passes=passes)
+    for top, passes, restarts in variants:
+        srch = dataclasses.replace(W.search, sweep_top=top, passes=passes, restarts=restarts,
+                                   init_steps=I.restart_steps(restarts, W.search.n_steps) if restarts else None)
         scr = P.Screener(dp, lib, P.DeviceSearch(srch))
         scr.run()
         torch.cuda.synchronize()
@@ -428,11 +431,12 @@ def budget_curve(args):
         k = max(1, int(round(0.01 * ok.sum())))
         top_ref = set(np.flatnonzero(ok)[np.lexsort((np.flatnonzero(ok), ref[ok]))[:k]].tolist())
         top_var = set(np.flatnonzero(ok)[np.lexsort((np.flatnonzero(ok), best[ok]))[:k]].tolist())
-        rows.append({"sweep_top": top, "passes": passes, "screen_ms": ms, "ligands_per_s": n_lig / (ms * 1e-3),
+        rows.append({"sweep_top": top, "passes": passes, "restarts": restarts, "screen_ms": ms,
+                     "ligands_per_s": n_lig / (ms * 1e-3),
                      "poses_per_s": poses / (ms * 1e-3), "mean_score_change": float(loss.mean()),
                      "worst_score_change": float(loss.max()), "best_of_full_or_better": float(np.mean(loss <= 1e-4 * np.maximum(1, np.abs(ref[ok])))),
                      "top1pct_overlap_with_full": len(top_ref & top_var) / k})
-        log(f"sweep_top={top} passes={passes}: {ms:.0f} ms, {n_lig / (ms * 1e-3):.0f} ligands/s, "
+        log(f"sweep_top={top} passes={passes} restarts={restarts}: {ms:.0f} ms, {n_lig / (ms * 1e-3):.0f} ligands/s, "
             f"mean change {loss.mean():+.3f}, top-1% overlap {len(top_ref & top_var) / k:.3f}")
     print(json.dumps({"metric": "search-budget speed/quality curve", "unit": "ligands/s",
                       "config": {"workload": f"first {n_lig} ligands of {W.name}", "reference": "sweep_top=0, passes=1"},

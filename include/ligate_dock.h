@@ -59,6 +59,7 @@ extern "C" {
 #define DOCK_MAX_STEPS 1024
 #define DOCK_MAX_TOP_STARTS 8192 /* starts ranked per ligand when sweep_top selects */
 #define DOCK_MAX_PASSES 16
+#define DOCK_MAX_RESTARTS 64     /* torsion restarts per rigid start */
 
 #define DOCK_LAYOUT_LINEAR 0     /* grids [t][z][y][x], FP32, x fastest */
 #define DOCK_LAYOUT_XY4 1        /* per node a 16-byte record of its z plane: G00 = G(x, y),
@@ -107,7 +108,12 @@ typedef struct {
  * scores lowest (FP32, ties to the lower start) get the greedy passes, which
  * needs n_quat*n_trans <= DOCK_MAX_TOP_STARTS; 0 or K >= n_quat*n_trans
  * searches from every start.  passes (0 or 1 = one; at most DOCK_MAX_PASSES)
- * repeats the pass over the torsions.
+ * repeats the pass over the torsions.  Torsion restarts: with restarts = R > 0
+ * (not combined with sweep_top) the search also starts from R turned copies of
+ * every rigid start; searched start e = r * n_quat*n_trans + p (r = 0 .. R) is
+ * rigid start p with, for r >= 1, each torsion k first turned by
+ * d_init_steps[r-1][k] in sweep order (a zero turn leaves it as it is).  The
+ * caller draws the initial turns, in [0, n_steps).
  */
 typedef struct {
     int32_t n_quat;
@@ -121,6 +127,8 @@ typedef struct {
     int32_t waves_per_block; /* 1, 2, 4 or 8; 0 = chosen by the library */
     int32_t sweep_top;       /* 0 = every start; K = the K best rigid starts */
     int32_t passes;          /* greedy passes over the torsions; 0 = 1 */
+    int32_t restarts;        /* R torsion restarts per rigid start, 0 .. DOCK_MAX_RESTARTS */
+    const int32_t *d_init_steps; /* [R][16] initial turns, device; NULL when R = 0 */
 } dock_search;
 
 /* Size in bytes of the grids for descriptor g. */
@@ -158,19 +166,22 @@ int dock_pack_ligands(const int32_t *d_atom_off, const float *d_xyz, const uint8
                       void *stream);
 
 /*
- * Docks every packed ligand: the rigid starts (all, or the sweep_top best),
- * each followed by the greedy torsion passes; per ligand the lowest final score
- * wins, ties to the lowest start.  Outputs, indexed by the ligand's position in
- * the packed library: d_best_score [n_lig] (+inf for a ligand whose status is
- * not OK), d_best_start [n_lig] (-1 if not OK), d_best_steps [n_lig][16] (each
- * torsion's total turn in sweep order: the sum of its chosen steps over the
- * passes, modulo n_steps; a turn changes only its own torsion angle, so the
- * final pose is the start with each torsion turned once by its total; unused
- * entries 0), optional d_start_scores [n_lig][n_quat*n_trans] (final score of
- * every searched start, +inf for starts not searched; NULL to skip), optional
- * d_start_steps [n_lig][n_quat*n_trans][16] (every searched start's totals;
- * NULL to skip), optional d_pose_count [1] (distinct poses scored: per docked
- * ligand n_quat*n_trans*(1 + passes*B*(n_steps-1)), or with sweep_top = K,
+ * Docks every packed ligand: the searched starts (every rigid start, or the
+ * sweep_top best, and their torsion restarts), each followed by the greedy
+ * torsion passes; per ligand the lowest final score wins, ties to the lowest
+ * searched start.  With N = (1 + restarts) * n_quat*n_trans searched starts,
+ * outputs, indexed by the ligand's position in the packed library:
+ * d_best_score [n_lig] (+inf for a ligand whose status is not OK),
+ * d_best_start [n_lig] (searched start e in [0, N); -1 if not OK),
+ * d_best_steps [n_lig][16] (each torsion's total turn in sweep order: its
+ * initial turn plus its chosen steps over the passes, modulo n_steps; a turn
+ * changes only its own torsion angle, so the final pose is rigid start
+ * e mod n_quat*n_trans with each torsion turned once by its total; unused
+ * entries 0), optional d_start_scores [n_lig][N] (final score of every
+ * searched start, +inf for starts not searched; NULL to skip), optional
+ * d_start_steps [n_lig][N][16] (every searched start's totals; NULL to skip),
+ * optional d_pose_count [1] (distinct poses scored: per docked ligand
+ * N*(1 + passes*B*(n_steps-1)), or with sweep_top = K,
  * n_quat*n_trans + K*passes*B*(n_steps-1)).  n_lig and n_atoms_total must match
  * the pack.  Workspace: query with d_ws == NULL.
  */

@@ -66,6 +66,8 @@ struct SearchC {
     float sw, swc;                  // sqrt(w) and sqrt(w) cut
     int top;                        // starts searched per ligand when they are selected (0: all)
     int passes;                     // greedy passes over the torsions (>= 1)
+    int restarts, N;                // torsion restarts per rigid start; searched starts (1 + restarts) QT
+    const int32_t *__restrict__ init;  // [restarts][16] initial turns
 };
 
 // Coordinates inside a start are in grid units (x - origin) / spacing throughout: the map is a
@@ -366,7 +368,7 @@ __device__ __forceinline__ void angle_table(int S, float (&cs)[APL], float (&sn)
     }
 }
 
-// Rigid start p in grid units: quaternion rotation of the reference, then the translation.
+// Rigid start p (< QT) in grid units: quaternion rotation of the reference, then the translation.
 __device__ __forceinline__ void place(const GridC &g, const SearchC &s, const LigLDS &L, int p, float (&cx)[2],
                                       float (&cy)[2], float (&cz)[2]) {
     const int lane = lane_id();
@@ -464,15 +466,63 @@ __device__ float direct_score(const GridC &g, rsrc_t rs, const SearchC &s, const
     return wave_sum(acc);
 }
 
-// The greedy passes from rigid start p.  Returns the final score (identical on all lanes);
-// lane k (< B) receives torsion k's total turn over the passes (modulo S) in `my_step`.  The
-// start's coordinates live in the wave's LDS copy W.pos (atom i at W.pos[i]), not in registers, so
-// that the lookups of a sweep run with fewer live registers.
+// Turns torsion k (axis and moving mask given) of the conformer in W.pos by step st of the lane
+// angle tables (the angle 2 pi st / S, held by lane st mod 64 in group st / 64).
+template <int APL>
+__device__ __forceinline__ void turn_torsion(WaveLDS &W, int n, const uint4 &mask, float xax, float xay, float xaz,
+                                             float ux, float uy, float uz, int st, const float (&cs)[APL],
+                                             const float (&sn)[APL]) {
+    const int lane = lane_id();
+    const int jb = st / kWave, owner = st - jb * kWave;
+    float csel = cs[0], ssel = sn[0];
+#pragma unroll
+    for (int j = 1; j < APL; ++j)
+        if (j == jb) {
+            csel = cs[j];
+            ssel = sn[j];
+        }
+    const float cb = __shfl(csel, owner), sb = __shfl(ssel, owner);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = lane + kWave * h;
+        if (i < n && mask_has(mask, i)) {
+            const float3 x = W.pos[i];
+            float px, py, pz, ax, ay, az, bx, by, bz;
+            circle(ux, uy, uz, xax, xay, xaz, x.x, x.y, x.z, px, py, pz, ax, ay, az, bx, by, bz);
+            W.pos[i] = make_float3(fmaf(ax, cb, fmaf(bx, sb, px)), fmaf(ay, cb, fmaf(by, sb, py)),
+                                   fmaf(az, cb, fmaf(bz, sb, pz)));
+        }
+    }
+    wave_sync();
+}
+
+// The conformer in W.pos scored from scratch (every atom's grid term and every clash pair).
+template <int BOUNDARY, int LAYOUT>
+__device__ float direct_score_lds(const GridC &g, rsrc_t rs, const SearchC &s, const LigLDS &L, const WaveLDS &W) {
+    const int lane = lane_id(), n = L.n;
+    float cx[2], cy[2], cz[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = lane + kWave * h;
+        const float3 x = i < n ? W.pos[i] : make_float3(0.0f, 0.0f, 0.0f);
+        cx[h] = x.x;
+        cy[h] = x.y;
+        cz[h] = x.z;
+    }
+    return direct_score<BOUNDARY, LAYOUT>(g, rs, s, L, cx, cy, cz);
+}
+
+// The greedy passes from searched start e (rigid start e mod QT; for restart r = e / QT >= 1,
+// each torsion first turned by its initial step).  Returns the final score (identical on all lanes);
+// lane k (< B) receives torsion k's total turn (initial turn and the passes, modulo S) in
+// `my_step`.  The start's coordinates live in the wave's LDS copy W.pos (atom i at W.pos[i]), not
+// in registers, so that the lookups of a sweep run with fewer live registers.
 template <int APL, int BOUNDARY, int LAYOUT>
-__device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const LigLDS &L, WaveLDS &W, int p,
+__device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const LigLDS &L, WaveLDS &W, int e,
                            float clash_ref, const float (&cs)[APL], const float (&sn)[APL], int &my_step) {
     const int lane = lane_id();
     const int n = L.n;
+    const int restart = s.restarts ? e / s.QT : 0, p = e - restart * s.QT;
     float eg = 0.0f;
     {
         float cx[2], cy[2], cz[2];
@@ -488,6 +538,22 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
     }
     wave_sync();
     float E = wave_sum(eg) + clash_ref;
+    my_step = 0;
+    if (restart > 0) {  // the restart's initial turns (a zero turn leaves the torsion as it is)
+        bool turned = false;
+        for (int k = 0; k < L.B; ++k) {
+            const int st = ((s.init[(restart - 1) * DOCK_MAX_TORSIONS + k] % s.S) + s.S) % s.S;
+            if (lane == k) my_step = st;
+            if (st == 0) continue;
+            turned = true;
+            const TorRec tr = L.tor[k];
+            float xax, xay, xaz, ux, uy, uz;
+            axis_lds(tr, W, xax, xay, xaz, ux, uy, uz);
+            turn_torsion<APL>(W, n, make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]), xax, xay, xaz,
+                              ux, uy, uz, st, cs, sn);
+        }
+        if (turned) E = direct_score_lds<BOUNDARY, LAYOUT>(g, rs, s, L, W);
+    }
     // The score is carried incrementally in FP32; when it passed through values much larger than
     // the final one (atoms far outside the box or clashing in the rigid pose), the cancellation
     // would cost accuracy, so the final conformer is then rescored from scratch.
@@ -497,7 +563,6 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
     constexpr int NJ = APL < 4 ? APL : 4;
     constexpr int NA = 4 / NJ;
 
-    my_step = 0;
     // the sweeps of all passes: torsion k runs 0..B-1 in every pass
     for (int sweep = 0, k = 0; sweep < s.passes * L.B; ++sweep, k = k + 1 == L.B ? 0 : k + 1) {
         const TorRec tr = L.tor[k];
@@ -685,44 +750,13 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
         Emax = fmaxf(Emax, fabsf(E));
 
         // apply the winning step
-        const int jb = sbest / kWave, owner = sbest - jb * kWave;
-        float csel = cs[0], ssel = sn[0];
-#pragma unroll
-        for (int j = 1; j < APL; ++j)
-            if (j == jb) {
-                csel = cs[j];
-                ssel = sn[j];
-            }
-        const float cb = __shfl(csel, owner), sb = __shfl(ssel, owner);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int i = lane + kWave * h;
-            if (i < n && mask_has(mask, i)) {
-                const float3 x = W.pos[i];
-                float px, py, pz, ax, ay, az, bx, by, bz;
-                circle(ux, uy, uz, xax, xay, xaz, x.x, x.y, x.z, px, py, pz, ax, ay, az, bx, by, bz);
-                W.pos[i] = make_float3(fmaf(ax, cb, fmaf(bx, sb, px)), fmaf(ay, cb, fmaf(by, sb, py)),
-                                       fmaf(az, cb, fmaf(bz, sb, pz)));
-            }
-        }
-        wave_sync();
+        turn_torsion<APL>(W, n, mask, xax, xay, xaz, ux, uy, uz, sbest, cs, sn);
         if (lane == k) {  // total turn of torsion k over the passes, modulo S
             my_step += sbest;
             my_step -= my_step >= s.S ? s.S : 0;
         }
     }
-    if (Emax > 16.0f * fmaxf(1.0f, fabsf(E))) {
-        float cx[2], cy[2], cz[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int i = lane + kWave * h;
-            const float3 x = i < n ? W.pos[i] : make_float3(0.0f, 0.0f, 0.0f);
-            cx[h] = x.x;
-            cy[h] = x.y;
-            cz[h] = x.z;
-        }
-        E = direct_score<BOUNDARY, LAYOUT>(g, rs, s, L, cx, cy, cz);
-    }
+    if (Emax > 16.0f * fmaxf(1.0f, fabsf(E))) E = direct_score_lds<BOUNDARY, LAYOUT>(g, rs, s, L, W);
     return E;
 }
 
@@ -755,8 +789,10 @@ __global__ void k_screen_init(uint64_t *best_key, int n_lig, uint32_t *counter, 
 
 // Planner: cost-descending order (ties by ligand index); invalid ligands last.  Poses: every
 // rigid start once, plus (S - 1) new poses per torsion sweep of each searched start.
-__global__ void k_screen_plan(const LigDesc *desc, int n_lig, int S, uint64_t *keys, uint64_t *pose_count, int QT,
-                              int n_searched, int passes) {
+// n_first: poses scored before the sweeps (every rigid start when starts are selected, otherwise
+// every searched start's first conformer).
+__global__ void k_screen_plan(const LigDesc *desc, int n_lig, int S, uint64_t *keys, uint64_t *pose_count,
+                              int n_first, int n_searched, int passes) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t poses = 0;
     if (l < n_lig) {
@@ -764,7 +800,7 @@ __global__ void k_screen_plan(const LigDesc *desc, int n_lig, int S, uint64_t *k
         uint64_t cost = 0;
         if (d.status == DOCK_LIG_OK) {
             cost = (uint64_t)d.n + (uint64_t)passes * ((uint64_t)(S - 1) * (uint64_t)d.sum_m + (uint64_t)d.n_pairs);
-            poses = (uint64_t)QT + (uint64_t)n_searched * (uint64_t)passes * (uint64_t)d.B * (uint64_t)(S - 1);
+            poses = (uint64_t)n_first + (uint64_t)n_searched * (uint64_t)passes * (uint64_t)d.B * (uint64_t)(S - 1);
         }
         if (cost > 0xffffffffull) cost = 0xffffffffull;
         keys[l] = ((uint64_t)(~(uint32_t)cost) << 32) | (uint32_t)l;
@@ -921,18 +957,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (L.status == DOCK_LIG_OK) {
             const float clash_ref = rigid_clash(L, A.s);
             uint64_t wbest = ~0ull;
-            const int p0 = batch * A.P, p1 = min(p0 + A.P, A.s.top ? A.s.top : A.s.QT);
+            const int p0 = batch * A.P, p1 = min(p0 + A.P, A.s.top ? A.s.top : A.s.N);
             for (int idx = p0 + w; idx < p1; idx += A.nw) {
-                // the full start set is enumerated translation-major (idx = it * n_quat + iq)
+                // the searched starts are enumerated restart by restart, each rigid start set
+                // translation-major (idx = r QT + it n_quat + iq)
+                const int rq = A.s.restarts ? idx % A.s.QT : idx;
                 const int p = A.s.top ? (int)A.sel[(size_t)lig * A.s.top + idx]
-                                      : (idx % A.s.n_quat) * A.s.n_trans + idx / A.s.n_quat;
+                                      : idx - rq + (rq % A.s.n_quat) * A.s.n_trans + rq / A.s.n_quat;
                 int step = 0;
                 const float E = run_start<APL, BOUNDARY, LAYOUT>(A.g, rs, A.s, L, W, p, clash_ref, cs, sn, step);
                 const uint64_t key = ((uint64_t)float_to_ordered(E) << 32) | (uint32_t)p;
                 wbest = key < wbest ? key : wbest;
-                if (A.start_scores && lane == 0) A.start_scores[(size_t)lig * A.s.QT + p] = E;
+                if (A.start_scores && lane == 0) A.start_scores[(size_t)lig * A.s.N + p] = E;
                 if (A.start_steps && lane < DOCK_MAX_TORSIONS)
-                    A.start_steps[((size_t)lig * A.s.QT + p) * DOCK_MAX_TORSIONS + lane] =
+                    A.start_steps[((size_t)lig * A.s.N + p) * DOCK_MAX_TORSIONS + lane] =
                         (uint16_t)(lane < L.B ? step : 0);
             }
             if (lane == 0) wbest_s[w] = wbest;
@@ -987,7 +1025,7 @@ __global__ __launch_bounds__(64) void k_score_poses(GridC g, SearchC s, PackView
     const int lane = lane_id();
     const int lig = d_lig[pose];
     const int p = d_start[pose];
-    if (lig < 0 || lig >= n_lig || p < 0 || p >= s.QT) {  // descriptor outside the library or start set
+    if (lig < 0 || lig >= n_lig || p < 0 || p >= s.N) {  // descriptor outside the library or start set
         if (lane == 0) out[pose] = NAN;
         return;
     }
@@ -1000,7 +1038,7 @@ __global__ __launch_bounds__(64) void k_score_poses(GridC g, SearchC s, PackView
     const rsrc_t rs = grid_rsrc(g);
     const int n = L.n;
     float cx[2], cy[2], cz[2];
-    place(g, s, L, p, cx, cy, cz);
+    place(g, s, L, p % s.QT, cx, cy, cz);  // the totals are turns from the rigid start
     for (int k = 0; k < L.B; ++k) {
         const TorRec tr = L.tor[k];
         const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
@@ -1146,7 +1184,7 @@ __global__ __launch_bounds__(64) void k_filter_rescore(RescoreArgs R) {
         // the pose, as k_score_poses builds it (grid units)
         const int n = L.n;
         float cx[2], cy[2], cz[2];
-        place(R.g, R.s, L, p, cx, cy, cz);
+        place(R.g, R.s, L, p % R.s.QT, cx, cy, cz);
         for (int k = 0; k < L.B; ++k) {
             const TorRec tr = L.tor[k];
             const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
@@ -1324,6 +1362,13 @@ static int check_search(const dock_search *s) {
     LIGATE_REQUIRE(s->sweep_top == 0 || s->sweep_top >= (int64_t)s->n_quat * s->n_trans ||
                        (int64_t)s->n_quat * s->n_trans <= DOCK_MAX_TOP_STARTS,
                    DOCK_ERR_LIMIT, "selecting sweep_top starts needs n_quat * n_trans <= %d", DOCK_MAX_TOP_STARTS);
+    LIGATE_REQUIRE(s->restarts >= 0 && s->restarts <= DOCK_MAX_RESTARTS, DOCK_ERR_INVALID_ARG,
+                   "restarts must be in [0, %d]", DOCK_MAX_RESTARTS);
+    LIGATE_REQUIRE(s->restarts == 0 || s->d_init_steps, DOCK_ERR_INVALID_ARG, "restarts need d_init_steps");
+    LIGATE_REQUIRE(s->restarts == 0 || s->sweep_top == 0, DOCK_ERR_INVALID_ARG,
+                   "torsion restarts are not combined with sweep_top");
+    LIGATE_REQUIRE((int64_t)s->n_quat * s->n_trans * (1 + s->restarts) < (1ll << 31), DOCK_ERR_LIMIT,
+                   "too many searched starts");
     return DOCK_OK;
 }
 
@@ -1345,6 +1390,9 @@ static SearchC make_search(const dock_search *d, float spacing) {
     s.swc = s.sw * s.cut;
     s.top = d->sweep_top > 0 && d->sweep_top < s.QT ? d->sweep_top : 0;
     s.passes = d->passes > 1 ? d->passes : 1;
+    s.restarts = d->restarts;
+    s.N = s.QT * (1 + d->restarts);
+    s.init = d->d_init_steps;
     return s;
 }
 
@@ -1470,12 +1518,12 @@ extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const
     if (P == 0) {
         // enough items to keep every block busy several times over, at most 256 starts per item
         const int64_t slots = (int64_t)default_cu_count() * 6;
-        const int64_t total = (int64_t)n_lig * (A.s.top ? A.s.top : A.s.QT);
+        const int64_t total = (int64_t)n_lig * (A.s.top ? A.s.top : A.s.N);
         int64_t want = total / (4 * slots);
         want = std::max<int64_t>(A.nw, std::min<int64_t>(256, want));
         P = (int)want;
     }
-    const int n_searched = A.s.top ? A.s.top : A.s.QT;
+    const int n_searched = A.s.top ? A.s.top : A.s.N;
     P = std::min(P, n_searched);
     A.P = P;
     A.bpl = (n_searched + P - 1) / P;
@@ -1483,8 +1531,9 @@ extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const
 
     const unsigned nb = (unsigned)((n_lig + 255) / 256);
     hipLaunchKernelGGL(k_screen_init, dim3(nb), dim3(256), 0, st, best_key, n_lig, counter, d_pose_count);
+    // every rigid start is scored once when starts are selected, every searched start's first pose otherwise
     hipLaunchKernelGGL(k_screen_plan, dim3(nb), dim3(256), 0, st, A.pk.desc, n_lig, A.s.S, order, d_pose_count,
-                       A.s.QT, n_searched, A.s.passes);
+                       A.s.top ? A.s.QT : A.s.N, n_searched, A.s.passes);
     rc = radix_sort_u64(order, n_lig, 32, 64, rws, st);
     if (rc) return rc;
     if (gd->layout == DOCK_LAYOUT_XY4)
@@ -1539,8 +1588,8 @@ extern "C" int dock_rescore(const dock_grid_desc *gd, const float *d_grids, cons
                    "bad library size");
     LIGATE_REQUIRE(n_keep >= 1 && n_keep <= kMaxKeep, DOCK_ERR_INVALID_ARG, "n_keep must be in [1, %d]", kMaxKeep);
     LIGATE_REQUIRE(rmsd_min >= 0.0f, DOCK_ERR_INVALID_ARG, "rmsd_min must be >= 0");
-    LIGATE_REQUIRE((int64_t)sd->n_quat * sd->n_trans <= DOCK_MAX_TOP_STARTS, DOCK_ERR_LIMIT,
-                   "picking poses needs n_quat * n_trans <= %d", DOCK_MAX_TOP_STARTS);
+    LIGATE_REQUIRE((int64_t)sd->n_quat * sd->n_trans * (1 + sd->restarts) <= DOCK_MAX_TOP_STARTS, DOCK_ERR_LIMIT,
+                   "picking poses needs at most %d searched starts", DOCK_MAX_TOP_STARTS);
     LIGATE_REQUIRE(n_prot >= 0 && (n_prot == 0 || (d_prot_xyz && d_prot_type)), DOCK_ERR_INVALID_ARG,
                    "protein arrays are NULL");
     LIGATE_REQUIRE(h_params && pot && pot->r_min > 0.0, DOCK_ERR_INVALID_ARG, "bad potential");
@@ -1554,7 +1603,7 @@ extern "C" int dock_rescore(const dock_grid_desc *gd, const float *d_grids, cons
     A.pk = PackView::of(d_pack, n_lig, n_atoms_total);
     A.n_lig = n_lig;
     hipLaunchKernelGGL(k_pick_poses, dim3((unsigned)n_lig), dim3(kTopBlock), 0, st, A.pk.desc, d_start_scores,
-                       A.s.QT, n_keep, d_pose_start);
+                       A.s.N, n_keep, d_pose_start);
     PoseArgs R{A, d_pose_start, d_pose_steps, d_pose_score, n_keep};
     const bool per = gd->boundary == DOCK_BOUNDARY_PERIODIC, xy4 = gd->layout == DOCK_LAYOUT_XY4;
     if (per && xy4) replay_apl<DOCK_BOUNDARY_PERIODIC, DOCK_LAYOUT_XY4>(A.s.S, R, n_lig, st);

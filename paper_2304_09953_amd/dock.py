@@ -49,7 +49,8 @@ class SearchDesc(ctypes.Structure):
     _fields_ = [("n_quat", ctypes.c_int32), ("d_quat", ctypes.c_void_p), ("n_trans", ctypes.c_int32),
                 ("d_trans", ctypes.c_void_p), ("n_steps", ctypes.c_int32), ("clash_cut", ctypes.c_float),
                 ("clash_w", ctypes.c_float), ("starts_per_item", ctypes.c_int32),
-                ("waves_per_block", ctypes.c_int32), ("sweep_top", ctypes.c_int32), ("passes", ctypes.c_int32)]
+                ("waves_per_block", ctypes.c_int32), ("sweep_top", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("d_init_steps", ctypes.c_void_p)]
 
 
 class DockError(RuntimeError):
@@ -116,10 +117,12 @@ def grid_desc(pocket, boundary: int = BOUNDARY_CLAMP, layout: int = LAYOUT_XY4) 
 
 def search_desc(d_quat: torch.Tensor, d_trans: torch.Tensor, n_steps: int, clash_cut: float = 2.5,
                 clash_w: float = 10.0, starts_per_item: int = 0, waves_per_block: int = 0, sweep_top: int = 0,
-                passes: int = 1) -> SearchDesc:
+                passes: int = 1, d_init_steps: torch.Tensor | None = None) -> SearchDesc:
+    """d_init_steps: int32 [R][16] initial turns of R torsion restarts per rigid start (device), or None."""
+    R = 0 if d_init_steps is None else d_init_steps.shape[0]
     return SearchDesc(d_quat.shape[0], d_quat.data_ptr(), d_trans.shape[0], d_trans.data_ptr(), int(n_steps),
                       float(clash_cut), float(clash_w), int(starts_per_item), int(waves_per_block), int(sweep_top),
-                      int(passes))
+                      int(passes), R, d_init_steps.data_ptr() if R else None)
 
 
 # ------------------------------------------------------------------------------------------------

@@ -103,12 +103,26 @@ class DeviceSearch:
         self.search = search
         self.quat = _dev(search.quat, device, torch.float32)
         self.trans = _dev(search.trans, device, torch.float32)
+        R = int(getattr(search, "restarts", 0))
+        self.init_steps = None
+        if R:
+            init = np.zeros((R, dock.MAX_TORSIONS), np.int32)
+            given = np.asarray(search.init_steps, dtype=np.int32).reshape(R, -1)
+            init[:, :given.shape[1]] = given
+            self.init_steps = _dev(init, device, torch.int32)
         self.desc = dock.search_desc(self.quat, self.trans, search.n_steps, search.clash_cut, search.clash_w,
-                                     starts_per_item, waves_per_block, search.sweep_top, search.passes)
+                                     starts_per_item, waves_per_block, search.sweep_top, search.passes,
+                                     self.init_steps)
 
     @property
     def n_starts(self) -> int:
+        """Rigid starts Q T."""
         return self.quat.shape[0] * self.trans.shape[0]
+
+    @property
+    def n_searched(self) -> int:
+        """Searched starts: the rigid starts and their torsion restarts."""
+        return self.n_starts * (1 + (0 if self.init_steps is None else self.init_steps.shape[0]))
 
 
 @dataclass
@@ -134,9 +148,9 @@ class Screener:
         self.best_start = torch.empty(n, dtype=torch.int32, device=dev)
         self.best_steps = torch.empty(n * dock.MAX_TORSIONS, dtype=torch.int16, device=dev)
         self.pose_count = torch.empty(1, dtype=torch.int64, device=dev)
-        self.start_scores = (torch.empty(n * search.n_starts, dtype=torch.float32, device=dev)
+        self.start_scores = (torch.empty(n * search.n_searched, dtype=torch.float32, device=dev)
                              if start_scores else None)
-        self.start_steps = (torch.empty(n * search.n_starts * dock.MAX_TORSIONS, dtype=torch.int16, device=dev)
+        self.start_steps = (torch.empty(n * search.n_searched * dock.MAX_TORSIONS, dtype=torch.int16, device=dev)
                             if start_scores else None)
 
     def run(self, stream=None) -> ScreenResult:

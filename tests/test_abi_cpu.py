@@ -153,6 +153,13 @@ def test_size_queries_and_argument_errors():
     all_of_many = dock.SearchDesc(4096, fake, 4, fake, 64, 2.5, 10.0, 0, 0, 16384, 1)  # nothing to select
     assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(all_of_many), None, None,
                            None, None, None, None, None, ctypes.byref(sz), None) == 0
+    # torsion restarts: at most DOCK_MAX_RESTARTS, need the initial-turn table, not with sweep_top
+    for R, init, top, code in ((2, fake, 0, 0), (64, fake, 0, 0), (65, fake, 0, -1), (-1, fake, 0, -1),
+                               (2, None, 0, -1), (2, fake, 5, -1)):
+        sr = dock.SearchDesc(4, fake, 2, fake, 64, 2.5, 10.0, 0, 0, top, 1, R, init)
+        assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(sr), None, None, None,
+                               None, None, None, None, ctypes.byref(sz), None) == code, (R, init, top)
+    assert "DOCK_MAX_RESTARTS 64" in open(os.path.join(ROOT, "include", "ligate_dock.h")).read()
     assert lib.dock_merge_pockets(fake, 0, 10, fake, fake, None) == -1
     assert lib.dock_merge_pockets(fake, 2, 0, fake, fake, None) == -1
     assert lib.dock_merge_pockets(None, 2, 10, fake, fake, None) == -1

@@ -26,13 +26,15 @@ def env():
     return P, W, pocket, ligs, P.DevicePocket(pocket), P.DeviceLibrary(ligs)
 
 
-@pytest.mark.parametrize("n_keep,rmsd_min,top,passes", [(8, 1.0, 0, 1), (16, 2.5, 40, 2), (3, 0.0, 0, 1)])
-def test_rescore_matches_oracle(env, n_keep, rmsd_min, top, passes):
+@pytest.mark.parametrize("n_keep,rmsd_min,top,passes,restarts",
+                         [(8, 1.0, 0, 1, 0), (16, 2.5, 40, 2, 0), (3, 0.0, 0, 1, 0), (8, 1.0, 0, 1, 2)])
+def test_rescore_matches_oracle(env, n_keep, rmsd_min, top, passes, restarts):
     P, W, pocket, ligs, dp, lib = env
-    srch = dataclasses.replace(W.search, sweep_top=top, passes=passes)
+    srch = dataclasses.replace(W.search, sweep_top=top, passes=passes, restarts=restarts,
+                               init_steps=I.restart_steps(restarts, W.search.n_steps) if restarts else None)
     ds = P.DeviceSearch(srch)
-    QT, n = srch.n_starts, ligs.n_lig
-    say(f"rescore: keep {n_keep}, rmsd_min {rmsd_min}, sweep_top {top}, passes {passes}")
+    QT, n = srch.n_searched, ligs.n_lig  # searched starts: with restarts, (1 + R) rigid-start sets
+    say(f"rescore: keep {n_keep}, rmsd_min {rmsd_min}, sweep_top {top}, passes {passes}, restarts {restarts}")
     scr = P.screen(dp, lib, ds, start_scores=True)
     res = P.rescore(dp, lib, ds, scr.start_scores.view(n, QT), n_keep, rmsd_min, want_xyz=True)
     torch.cuda.synchronize()

@@ -1,5 +1,5 @@
 """Search-budget variants on the GPU against the oracle: torsion sweeps from only the K best
-rigid starts, and several greedy passes over the torsions."""
+rigid starts, several greedy passes over the torsions, and torsion restarts of every rigid start."""
 import dataclasses
 
 import numpy as np
@@ -36,7 +36,7 @@ def _screen(P, dp, ligs, srch):
     return {"score": r.best_score.cpu().numpy().astype(np.float64), "start": r.best_start.cpu().numpy(),
             "steps": P.steps_numpy(r.best_steps), "poses": int(r.pose_count.cpu().item()),
             "finals": r.start_scores.cpu().numpy().reshape(n, -1).astype(np.float64),
-            "start_steps": P.steps_numpy(r.start_steps).reshape(n, srch.n_starts, -1)}
+            "start_steps": P.steps_numpy(r.start_steps).reshape(n, srch.n_searched, -1)}
 
 
 @pytest.mark.parametrize("top,passes", [(16, 1), (0, 2), (40, 3)])
@@ -84,3 +84,38 @@ def test_selecting_every_start_is_the_plain_search(env):
         r = _screen(P, dp, ligs, dataclasses.replace(W.search, sweep_top=K))
         for key in ("score", "start", "steps", "finals", "start_steps", "poses"):
             assert np.array_equal(np.asarray(r[key]), np.asarray(base[key])), key
+
+
+@pytest.mark.parametrize("restarts,passes", [(2, 1), (3, 2)])
+def test_restarts_match_oracle(env, restarts, passes):
+    P, W, pocket, G, ligs, dp = env
+    srch = dataclasses.replace(W.search, passes=passes, restarts=restarts,
+                               init_steps=I.restart_steps(restarts, W.search.n_steps))
+    N, QT = srch.n_searched, srch.n_starts
+    say(f"pocket48-lib100 subset of 20: {restarts} torsion restarts per start, passes={passes}")
+    g = _screen(P, dp, ligs, srch)
+    orc = oracle.dock(pocket, G, ligs, srch, per_start=True)
+    assert g["finals"].shape == (ligs.n_lig, N) and np.all(np.isfinite(g["finals"]))
+    st = check_per_start(pocket, G, ligs, srch, g["finals"], g["start_steps"], orc)
+    say(f"per-start: {st}")
+    assert st["agree"] >= 0.99 * st["starts"]
+    assert np.array_equal(g["score"], g["finals"].min(1)) and np.array_equal(g["start"], np.argmin(g["finals"], 1))
+    sel = np.arange(ligs.n_lig)
+    check_exact_and_valid(pocket, G, ligs, srch, sel, g["score"], g["start"], g["steps"])
+    n_flag = check_optimal(pocket, G, ligs, srch, sel, g["score"], g["start"], orc)
+    say(f"{n_flag} ligands with near-ties; restart winners: {int(np.sum(g['start'] >= QT))} of {ligs.n_lig}")
+    B = ligs.n_rot
+    assert g["poses"] == int(np.sum(N * (1 + passes * B * (srch.n_steps - 1))))
+
+
+def test_zero_restarts_repeat_the_plain_search(env):
+    P, W, pocket, G, ligs, dp = env
+    say("two restarts with zero initial turns against the plain search")
+    base = _screen(P, dp, ligs, W.search)
+    r = _screen(P, dp, ligs, dataclasses.replace(W.search, restarts=2, init_steps=np.zeros((2, 16), np.int32)))
+    QT = W.search.n_starts
+    for k in range(3):
+        assert np.array_equal(r["finals"][:, k * QT:(k + 1) * QT], base["finals"])
+        assert np.array_equal(r["start_steps"][:, k * QT:(k + 1) * QT], base["start_steps"])
+    for key in ("score", "start", "steps"):
+        assert np.array_equal(np.asarray(r[key]), np.asarray(base[key])), key
