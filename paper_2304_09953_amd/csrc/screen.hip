@@ -760,6 +760,35 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
     return E;
 }
 
+// The pose (searched start e, total turns steps[k] of torsion k in sweep order) in registers, grid
+// units: rigid start e mod QT, then each torsion turned once by its total.  The angles are formed
+// here with sincospif (dock_score_poses and the rescoring path share this code, so they build the
+// same conformers).
+__device__ __forceinline__ void build_pose(const GridC &g, const SearchC &s, const LigLDS &L, int e,
+                                           const uint16_t *steps, float (&cx)[2], float (&cy)[2], float (&cz)[2]) {
+    const int lane = lane_id(), n = L.n;
+    place(g, s, L, e % s.QT, cx, cy, cz);
+    for (int k = 0; k < L.B; ++k) {
+        const TorRec tr = L.tor[k];
+        const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
+        float xax, xay, xaz, ux, uy, uz;
+        axis(tr, cx, cy, cz, xax, xay, xaz, ux, uy, uz);
+        float sb, cb;
+        sincospif(2.0f * (float)steps[k] / (float)s.S, &sb, &cb);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = lane + kWave * h;
+            if (i < n && mask_has(mask, i)) {
+                float px, py, pz, ax, ay, az, bx, by, bz;
+                circle(ux, uy, uz, xax, xay, xaz, cx[h], cy[h], cz[h], px, py, pz, ax, ay, az, bx, by, bz);
+                cx[h] = fmaf(ax, cb, fmaf(bx, sb, px));
+                cy[h] = fmaf(ay, cb, fmaf(by, sb, py));
+                cz[h] = fmaf(az, cb, fmaf(bz, sb, pz));
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------------------------
@@ -1036,29 +1065,8 @@ __global__ __launch_bounds__(64) void k_score_poses(GridC g, SearchC s, PackView
         return;
     }
     const rsrc_t rs = grid_rsrc(g);
-    const int n = L.n;
     float cx[2], cy[2], cz[2];
-    place(g, s, L, p % s.QT, cx, cy, cz);  // the totals are turns from the rigid start
-    for (int k = 0; k < L.B; ++k) {
-        const TorRec tr = L.tor[k];
-        const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
-        float xax, xay, xaz, ux, uy, uz;
-        axis(tr, cx, cy, cz, xax, xay, xaz, ux, uy, uz);
-        const int st = d_steps[pose * DOCK_MAX_TORSIONS + k];
-        float sb, cb;
-        sincospif(2.0f * (float)st / (float)s.S, &sb, &cb);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int i = lane + kWave * h;
-            if (i < n && mask_has(mask, i)) {
-                float px, py, pz, ax, ay, az, bx, by, bz;
-                circle(ux, uy, uz, xax, xay, xaz, cx[h], cy[h], cz[h], px, py, pz, ax, ay, az, bx, by, bz);
-                cx[h] = fmaf(ax, cb, fmaf(bx, sb, px));
-                cy[h] = fmaf(ay, cb, fmaf(by, sb, py));
-                cz[h] = fmaf(az, cb, fmaf(bz, sb, pz));
-            }
-        }
-    }
+    build_pose(g, s, L, p, d_steps + pose * DOCK_MAX_TORSIONS, cx, cy, cz);
     // every atom's grid term and every clash pair, from the final coordinates
     const float acc = direct_score<BOUNDARY, LAYOUT>(g, rs, s, L, cx, cy, cz);
     if (lane == 0) out[pose] = acc;
@@ -1184,26 +1192,7 @@ __global__ __launch_bounds__(64) void k_filter_rescore(RescoreArgs R) {
         // the pose, as k_score_poses builds it (grid units)
         const int n = L.n;
         float cx[2], cy[2], cz[2];
-        place(R.g, R.s, L, p % R.s.QT, cx, cy, cz);
-        for (int k = 0; k < L.B; ++k) {
-            const TorRec tr = L.tor[k];
-            const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
-            float xax, xay, xaz, ux, uy, uz;
-            axis(tr, cx, cy, cz, xax, xay, xaz, ux, uy, uz);
-            float sb, cb;
-            sincospif(2.0f * (float)R.pose_steps[slot * DOCK_MAX_TORSIONS + k] / (float)R.s.S, &sb, &cb);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int a = lane + kWave * h;
-                if (a < n && mask_has(mask, a)) {
-                    float px, py, pz, ax, ay, az, bx, by, bz;
-                    circle(ux, uy, uz, xax, xay, xaz, cx[h], cy[h], cz[h], px, py, pz, ax, ay, az, bx, by, bz);
-                    cx[h] = fmaf(ax, cb, fmaf(bx, sb, px));
-                    cy[h] = fmaf(ay, cb, fmaf(by, sb, py));
-                    cz[h] = fmaf(az, cb, fmaf(bz, sb, pz));
-                }
-            }
-        }
+        build_pose(R.g, R.s, L, p, R.pose_steps + slot * DOCK_MAX_TORSIONS, cx, cy, cz);
         // world coordinates in FP64: x = origin + h u
         double wx[2], wy[2], wz[2];
 #pragma unroll
