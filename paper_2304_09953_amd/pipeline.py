@@ -5,6 +5,7 @@ Holds PyTorch device tensors (memory and streams only) and calls the C ABI in
 """
 from __future__ import annotations
 
+import hashlib
 from dataclasses import dataclass
 
 import numpy as np
@@ -123,6 +124,16 @@ class DeviceSearch:
     def n_searched(self) -> int:
         """Searched starts: the rigid starts and their torsion restarts."""
         return self.n_starts * (1 + (0 if self.init_steps is None else self.init_steps.shape[0]))
+
+    def desc_fields(self) -> dict:
+        """The search's parameters, with a hash of its start sets (identifies the search in a manifest)."""
+        h = hashlib.sha256()
+        for t in (self.quat, self.trans) + (() if self.init_steps is None else (self.init_steps,)):
+            h.update(t.cpu().numpy().tobytes())
+        d = self.desc
+        return {"n_quat": d.n_quat, "n_trans": d.n_trans, "n_steps": d.n_steps, "clash_cut": d.clash_cut,
+                "clash_w": d.clash_w, "sweep_top": d.sweep_top, "passes": d.passes, "restarts": d.restarts,
+                "starts": h.hexdigest()[:16]}
 
 
 @dataclass

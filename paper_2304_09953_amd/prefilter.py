@@ -9,12 +9,22 @@ by data the workflow itself generates, §2).
    global top fraction by prediction, docking of the selected ligands only.
 5. Recall of the true top 1 % of a fully docked sample.
 
+Training and the streamed pass can checkpoint to a directory: a manifest of the run's parameters,
+then one file per finished unit (a member's epoch: weights, Adam moments and early-stopping state; a
+library chunk: predictions, or docking scores).  A rerun with the same directory and parameters
+resumes after the last finished unit, and its results equal an uninterrupted run's, since every unit
+is a pure function of seeded inputs and the state before it.  LIGATE_FAIL_AT makes a run raise before
+a named unit (the test hook of that path).
+
 Every computational step of a network runs in the library's kernels; this module orders the calls,
 moves ligand chunks between host and device, and does the host-side bookkeeping (the members' mean,
 validation error, ranks and recall).
 """
 from __future__ import annotations
 
+import hashlib
+import json
+import os
 import time
 from dataclasses import dataclass, field
 
@@ -42,6 +52,59 @@ def library_chunk(dist, n_types, first_id: int, n: int, stream: str = "lib"):
     return I.make_ligands(n, dist, n_types, stream=stream, first_id=first_id)
 
 
+class Checkpoint:
+    """Per-chunk results of a streamed pass in a directory, with a manifest of the run's parameters.
+
+    Opening a directory whose manifest differs from `params` raises: a resumed run must be the same run.
+    A chunk's arrays are written to a temporary file and renamed, so a file present is complete."""
+
+    def __init__(self, directory: str | None, params: dict):
+        self.dir = directory
+        if directory is None:
+            return
+        os.makedirs(directory, exist_ok=True)
+        path = os.path.join(directory, "manifest.json")
+        if os.path.exists(path):
+            with open(path) as f:
+                old = json.load(f)
+            if old != params:
+                raise ValueError(f"checkpoint directory {directory} holds another run: {old} != {params}")
+        else:
+            with open(path + ".tmp", "w") as f:
+                json.dump(params, f, sort_keys=True)
+            os.replace(path + ".tmp", path)
+
+    def _path(self, name: str) -> str:
+        return os.path.join(self.dir, name + ".npz")
+
+    def load(self, name: str) -> dict | None:
+        if self.dir is None or not os.path.exists(self._path(name)):
+            return None
+        with np.load(self._path(name)) as z:
+            return {k: z[k] for k in z.files}
+
+    def save(self, name: str, **arrays) -> None:
+        if self.dir is None:
+            return
+        tmp = self._path(name) + ".tmp.npz"
+        np.savez(tmp, **arrays)
+        os.replace(tmp, self._path(name))
+
+
+def _fail_hook(tag: str) -> None:
+    """Raises when LIGATE_FAIL_AT names this unit of work: "predict:<chunk>", "dock:<chunk>" or
+    "train:<member>:<epoch>" (chunks counted from 0 in library order)."""
+    if os.environ.get("LIGATE_FAIL_AT") == tag:
+        raise RuntimeError(f"LIGATE_FAIL_AT: injected failure before {tag}")
+
+
+def _digest(*arrays) -> str:
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()[:16]
+
+
 @dataclass
 class Surrogate:
     models: list
@@ -57,6 +120,16 @@ class Surrogate:
         """Mean of the members' outputs (z-scores of the best docking score) for BF16 features."""
         return np.mean([m.predict(xb).cpu().numpy().astype(np.float64) for m in self.models], axis=0)
 
+    def fingerprint(self) -> str:
+        """Hash of the members' weights and the input normalisation (identifies a trained filter)."""
+        h = hashlib.sha256()
+        for m in self.models:
+            h.update(m.master.cpu().numpy().tobytes())
+        h.update(self.mean.cpu().numpy().tobytes())
+        h.update(self.istd.cpu().numpy().tobytes())
+        h.update(np.array([self.y_mean, self.y_std]).tobytes())
+        return h.hexdigest()[:16]
+
     def predict_library(self, lib_dev) -> np.ndarray:
         """Predicted best score of every ligand of a DeviceLibrary, as the ensemble's z-score (a
         monotone map of the score, so rankings are those of the scores); +inf where the ligand's
@@ -68,13 +141,14 @@ class Surrogate:
 
 def train_surrogate(pocket_dev, search_dev, train_ligs, labels: np.ndarray | None = None, n_holdout: int = 40_000,
                     n_val: int | None = None, members: int = 4, max_epochs: int = 20, batch: int = 1024,
-                    lr: float = 1e-3, seed: int = 0, log=None) -> Surrogate:
+                    lr: float = 1e-3, seed: int = 0, log=None, checkpoint_dir: str | None = None) -> Surrogate:
     """Labels the training library by docking (unless given) and splits it, in order, into training,
     validation (n_val, default n_holdout / 2) and held-out (n_holdout) ligands.  Feature statistics
     come from the training part.  Each of `members` networks (its own seed for the initial weights
     and the sample order) trains for up to max_epochs and keeps the weights of the epoch with the
     lowest validation error (early stopping); the prediction is the members' mean.  Reports
-    held-out R^2 and Spearman.  The generated libraries hold valid ligands only."""
+    held-out R^2 and Spearman.  The generated libraries hold valid ligands only.  With
+    checkpoint_dir, every finished epoch is kept there and a rerun resumes after the last one."""
     n_val = n_holdout // 2 if n_val is None else n_val
     t0 = time.perf_counter()
     if labels is None:
@@ -93,12 +167,26 @@ def train_surrogate(pocket_dev, search_dev, train_ligs, labels: np.ndarray | Non
     z = torch.as_tensor(((y - y_mean) / y_std).astype(np.float32), device=Xb.device)
     Xtr, ztr = Xb[:n_tr], z[:n_tr]
     Xva, zva = Xb[n_tr:n_tr + n_val], (y[n_tr:n_tr + n_val] - y_mean) / y_std
+    ck = Checkpoint(checkpoint_dir, {"kind": "train", "n_lig": int(train_ligs.n_lig), "n_holdout": n_holdout,
+                                     "n_val": n_val, "members": members, "max_epochs": max_epochs, "batch": batch,
+                                     "lr": lr, "seed": seed, "labels": _digest(labels, train_ligs.ids)})
     t1 = time.perf_counter()
     models, best_epochs, hist = [], [], []
     for mbr in range(members):
         model = SG.Model(I.mlp_init(seed=seed + mbr))
         best, best_ep, best_w = np.inf, -1, model.master.clone()
-        for ep in range(max_epochs):
+        first = 0
+        for ep in range(max_epochs - 1, -1, -1):  # resume after the last finished epoch
+            done = ck.load(f"train_{mbr}_{ep}")
+            if done is not None:
+                model.load_state(done)
+                best_w.copy_(torch.as_tensor(done["best_w"]).to(best_w.device))
+                best, best_ep, first = float(done["best"]), int(done["best_ep"]), ep + 1
+                if mbr == 0:
+                    hist = done["hist"].tolist()
+                break
+        for ep in range(first, max_epochs):
+            _fail_hook(f"train:{mbr}:{ep}")
             h = SG.train(model, Xtr, ztr, epochs=1, batch=batch, lr=lr, seed=(seed + mbr) * 100003 + ep)
             if mbr == 0:
                 hist += h
@@ -107,6 +195,9 @@ def train_surrogate(pocket_dev, search_dev, train_ligs, labels: np.ndarray | Non
                 if err < best:
                     best, best_ep = err, ep
                     best_w.copy_(model.master)
+            if ck.dir is not None:
+                ck.save(f"train_{mbr}_{ep}", **model.state(), best_w=best_w.cpu().numpy(), best=np.array(best),
+                        best_ep=np.array(best_ep), hist=np.array(hist if mbr == 0 else [], np.float64))
             if log:
                 log(f"member {mbr}, epoch {ep + 1}/{max_epochs}: train loss {h[0]:.4f}" +
                     (f", validation {err:.4f}" if n_val else ""))
@@ -133,15 +224,29 @@ def train_surrogate(pocket_dev, search_dev, train_ligs, labels: np.ndarray | Non
 
 
 def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, n_lib: int, chunk: int, frac: float,
-                    stream: str = "lib", sample_every: int = 0, log=None) -> dict:
+                    stream: str = "lib", sample_every: int = 0, log=None, checkpoint_dir: str | None = None) -> dict:
     """Predicts every ligand of the streamed library and docks the global top `frac` by
     prediction.  With sample_every > 0 the ligands whose id is a multiple of it are also docked in
-    full during the same pass (the recall sample; timed separately).  Returns ids, scores, timings."""
+    full during the same pass (the recall sample; timed separately).  With checkpoint_dir, finished
+    chunks are kept there and skipped on a rerun of the same run.  Returns ids, scores, timings
+    (timings cover the chunks computed in this call)."""
+    ck = Checkpoint(checkpoint_dir, {"kind": "screen", "n_lib": n_lib, "chunk": chunk, "frac": frac, "stream": stream,
+                                     "sample_every": sample_every, "n_types": n_types, "dist": repr(dist),
+                                     "filter": sur.fingerprint(), "search": search_dev.desc_fields()})
     preds = np.empty(n_lib, dtype=np.float32)
     n_atoms = np.empty(n_lib, dtype=np.int16)
     t_gen = t_pred = t_sample = 0.0
     s_ids, s_scores = [], []
-    for s in range(0, n_lib, chunk):
+    for ci, s in enumerate(range(0, n_lib, chunk)):
+        done = ck.load(f"predict_{ci}")
+        if done is not None:
+            preds[s:s + len(done["preds"])] = done["preds"]
+            n_atoms[s:s + len(done["preds"])] = done["n_atoms"]
+            if sample_every:
+                s_ids.append(done["sample_ids"])
+                s_scores.append(done["sample_scores"])
+            continue
+        _fail_hook(f"predict:{ci}")
         g0 = time.perf_counter()
         ligs = library_chunk(dist, n_types, s, min(chunk, n_lib - s), stream)
         t_gen += time.perf_counter() - g0
@@ -158,6 +263,9 @@ def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, 
             s_scores.append(P.screen(pocket_dev, P.DeviceLibrary(sub), search_dev).best_score.cpu().numpy())
             t_sample += time.perf_counter() - d0
             s_ids.append(sub.ids)
+        e = s + ligs.n_lig
+        ck.save(f"predict_{ci}", preds=preds[s:e], n_atoms=n_atoms[s:e],
+                **({"sample_ids": s_ids[-1], "sample_scores": s_scores[-1]} if sample_every else {}))
         if log:
             log(f"predicted {s + ligs.n_lig}/{n_lib}" + (f", docked sample {sum(map(len, s_ids))}" if sample_every else ""))
     n_sel = int(round(frac * n_lib))
@@ -168,10 +276,15 @@ def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, 
     # dock the selection, regenerated chunk by chunk
     scores = np.empty(len(sel), dtype=np.float32)
     t_dock = 0.0
-    for s in range(0, n_lib, chunk):
+    for ci, s in enumerate(range(0, n_lib, chunk)):
         part = (sel >= s) & (sel < s + chunk)
         if not part.any():
             continue
+        done = ck.load(f"dock_{ci}")
+        if done is not None:
+            scores[part] = done["scores"]
+            continue
+        _fail_hook(f"dock:{ci}")
         g0 = time.perf_counter()
         ligs = library_chunk(dist, n_types, s, min(chunk, n_lib - s), stream).subset(sel[part] - s)
         t_gen += time.perf_counter() - g0
@@ -179,6 +292,7 @@ def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, 
         d0 = time.perf_counter()
         scores[part] = P.screen(pocket_dev, P.DeviceLibrary(ligs), search_dev).best_score.cpu().numpy()
         t_dock += time.perf_counter() - d0
+        ck.save(f"dock_{ci}", scores=scores[part])
         if log:
             log(f"docked selection up to id {s + chunk}")
     out = {"selected_ids": sel, "selected_scores": scores, "predictions": preds, "n_atoms": n_atoms,

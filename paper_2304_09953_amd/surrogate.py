@@ -135,6 +135,20 @@ class Model:
         self.step += 1
         _check(_lib().surr_adam(ctypes.byref(self.c), lr, b1, b2, eps, self.step, _s(stream)), "surr_adam")
 
+    def state(self) -> dict:
+        """Training state: FP32 master weights, Adam moments and step count.  The BF16 copies follow
+        from the master weights and the gradient buffer is overwritten by every step, so restoring
+        these continues training exactly."""
+        return {"master": self.master.cpu().numpy().copy(), "m": self.m.cpu().numpy().copy(),
+                "v": self.v.cpu().numpy().copy(), "step": np.array(self.step)}
+
+    def load_state(self, st: dict) -> None:
+        for name in ("master", "m", "v"):
+            t = getattr(self, name)
+            t.copy_(torch.as_tensor(np.asarray(st[name], dtype=np.float32)).to(t.device))
+        self.step = int(st["step"])
+        self.cast()
+
     def predict(self, x_bf16: torch.Tensor, chunk: int = 65536) -> torch.Tensor:
         out = torch.empty(x_bf16.shape[0], dtype=torch.float32, device=x_bf16.device)
         for s in range(0, x_bf16.shape[0], chunk):

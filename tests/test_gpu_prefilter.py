@@ -1,5 +1,6 @@
 """The learned pre-filter end to end on the GPU: what the trained network gains over selecting
-without it, and the filtered workflow's selection and docking against plain docking."""
+without it, the filtered workflow's selection and docking against plain docking, and runs that fail
+at a named unit of work and resume from their checkpoint directory."""
 import numpy as np
 import pytest
 import torch
@@ -60,3 +61,43 @@ def test_filtered_screen_selects_by_prediction_and_docks_like_plain(trained):
     c = PF.recall_curve(PF.ranks(preds)[res["sample_ids"]], res["sample_scores"].astype(np.float64), [0.2], 3000,
                         top=0.05)
     assert r == c[0.2]
+
+
+def test_filtered_screen_resumes_after_a_failure(trained, tmp_path, monkeypatch):
+    P, PF, W, dp, ds, ligs, sur = trained
+    args = (sur, dp, ds, W.dist, W.n_types, 2500, 1000, 0.2)
+    kw = dict(stream="tiny", sample_every=4)
+    say("filtered screen of 2500 ligands, uninterrupted, then failing before prediction chunk 1 and dock chunk 2")
+    ref = PF.filtered_screen(*args, **kw)
+    d = str(tmp_path / "screen")
+    for tag in ("predict:1", "dock:2"):
+        monkeypatch.setenv("LIGATE_FAIL_AT", tag)
+        with pytest.raises(RuntimeError, match=tag):
+            PF.filtered_screen(*args, **kw, checkpoint_dir=d)
+    monkeypatch.delenv("LIGATE_FAIL_AT")
+    res = PF.filtered_screen(*args, **kw, checkpoint_dir=d)
+    for key in ("selected_ids", "selected_scores", "predictions", "n_atoms", "sample_ids", "sample_scores"):
+        assert np.array_equal(res[key], ref[key]), key
+    with pytest.raises(ValueError, match="another run"):
+        PF.filtered_screen(sur, dp, ds, W.dist, W.n_types, 2500, 1000, 0.3, **kw, checkpoint_dir=d)
+
+
+def test_training_resumes_after_a_failure(trained, tmp_path, monkeypatch):
+    P, PF, W, dp, ds, ligs, sur = trained
+    sub = I.make_ligands(3000, W.dist, W.n_types, stream="train")
+    labels = PF.dock_scores(dp, ds, sub)
+    kw = dict(labels=labels, n_holdout=500, n_val=300, members=2, max_epochs=3, batch=256)
+    say("train a 2-member ensemble for 3 epochs, uninterrupted, then failing before member 1's epoch 1")
+    ref = PF.train_surrogate(dp, ds, sub, **kw)
+    d = str(tmp_path / "train")
+    monkeypatch.setenv("LIGATE_FAIL_AT", "train:1:1")
+    with pytest.raises(RuntimeError, match="train:1:1"):
+        PF.train_surrogate(dp, ds, sub, **kw, checkpoint_dir=d)
+    monkeypatch.delenv("LIGATE_FAIL_AT")
+    res = PF.train_surrogate(dp, ds, sub, **kw, checkpoint_dir=d)
+    for a, b in zip(ref.models, res.models):
+        assert torch.equal(a.master, b.master) and torch.equal(a.bf16, b.bf16)
+    assert res.metrics["best_epochs"] == ref.metrics["best_epochs"]
+    assert res.metrics["loss_first_epoch"] == ref.metrics["loss_first_epoch"]
+    assert res.metrics["loss_last_epoch"] == ref.metrics["loss_last_epoch"]
+    assert np.array_equal(res.holdout_pred, ref.holdout_pred)

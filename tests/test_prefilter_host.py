@@ -1,6 +1,9 @@
 """Host-side selection logic of the pre-filter workflow (no GPU): ranks, recall curves and the
-calibration of the docked fraction."""
+calibration of the docked fraction, the checkpoint directory and the failure hook."""
+import os
+
 import numpy as np
+import pytest
 
 from paper_2304_09953_amd import prefilter as PF
 
@@ -36,3 +39,37 @@ def test_calibrate_fraction():
     assert PF.recall_curve(r, true, [f], 4000)[f] >= 0.95
     assert list(PF.recall_curve(r, true, [f - 0.005], 4000).values())[0] < 0.95
     assert PF.calibrate_fraction(-true, true, 0.95) == 1.0
+
+
+def test_checkpoint_round_trip_and_manifest(tmp_path):
+    d = str(tmp_path / "ck")
+    params = {"kind": "screen", "n_lib": 10, "frac": 0.25, "search": {"n_steps": 8, "starts": "ab"}}
+    ck = PF.Checkpoint(d, params)
+    assert ck.load("predict_0") is None
+    a = np.arange(5, dtype=np.float32)
+    ck.save("predict_0", preds=a, n_atoms=np.array([3, 4], np.int16))
+    got = PF.Checkpoint(d, dict(params)).load("predict_0")  # a rerun with equal parameters sees it
+    assert np.array_equal(got["preds"], a) and got["preds"].dtype == np.float32
+    assert got["n_atoms"].tolist() == [3, 4]
+    assert sorted(os.listdir(d)) == ["manifest.json", "predict_0.npz"]  # no temporary file left behind
+    for key, val in (("frac", 0.5), ("search", {"n_steps": 8, "starts": "ac"})):
+        with pytest.raises(ValueError, match="another run"):
+            PF.Checkpoint(d, {**params, key: val})
+    # a file interrupted before its rename is not taken for a finished unit
+    with open(os.path.join(d, "predict_1.npz.tmp.npz"), "wb") as f:
+        f.write(b"PK\x03")
+    assert PF.Checkpoint(d, params).load("predict_1") is None
+    # no directory: nothing is written or found
+    none = PF.Checkpoint(None, params)
+    none.save("x", a=a)
+    assert none.load("x") is None
+
+
+def test_fail_hook_raises_only_for_the_named_unit(monkeypatch):
+    monkeypatch.delenv("LIGATE_FAIL_AT", raising=False)
+    PF._fail_hook("predict:0")
+    monkeypatch.setenv("LIGATE_FAIL_AT", "dock:2")
+    PF._fail_hook("dock:1")
+    PF._fail_hook("predict:2")
+    with pytest.raises(RuntimeError, match="dock:2"):
+        PF._fail_hook("dock:2")
