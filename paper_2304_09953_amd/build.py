@@ -22,7 +22,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # have given silently wrong results.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-munsafe-fp-atomics", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+             "-munsafe-fp-atomics", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+             "-L", "/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def build_library(verbose: bool = False, extra=()) -> str:

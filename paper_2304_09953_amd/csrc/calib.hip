@@ -53,6 +53,7 @@ __global__ __launch_bounds__(kCalibBlock) void k_calib_read(const float4 *__rest
 using namespace ligate;
 
 extern "C" int calib_fma_f32(int32_t blocks, int32_t iters, float *d_out, void *stream) {
+    LIGATE_ABI_RANGE();
     LIGATE_REQUIRE(blocks >= 1 && blocks <= (1 << 20) && iters >= 1 && iters <= (1 << 24), DOCK_ERR_INVALID_ARG,
                    "blocks or iters out of range");
     LIGATE_REQUIRE(d_out != nullptr, DOCK_ERR_INVALID_ARG, "d_out is NULL");
@@ -63,6 +64,7 @@ extern "C" int calib_fma_f32(int32_t blocks, int32_t iters, float *d_out, void *
 
 extern "C" int calib_cache_read(const void *d_buf, size_t bytes, int32_t reps, int32_t blocks, float *d_out,
                                 void *stream) {
+    LIGATE_ABI_RANGE();
     LIGATE_REQUIRE(d_buf && d_out, DOCK_ERR_INVALID_ARG, "NULL argument");
     LIGATE_REQUIRE(((uintptr_t)d_buf & 15u) == 0 && bytes >= 16384 && bytes % 16384 == 0 && bytes < (1ull << 34),
                    DOCK_ERR_INVALID_ARG, "bytes must be a positive multiple of 16384 (buffer 16-byte aligned)");

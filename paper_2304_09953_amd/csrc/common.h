@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 #include <stdio.h>
 
@@ -10,6 +11,17 @@
 namespace ligate {
 
 constexpr int kWave = 64;
+
+// A roctx range named after the C ABI function it spans, opened on entry and closed on every
+// return: rocprofv3 --marker-trace shows each call with the kernels it enqueued.  Without a
+// profiler attached the two calls do nothing.
+struct AbiRange {
+    explicit AbiRange(const char *name) { roctxRangePushA(name); }
+    ~AbiRange() { roctxRangePop(); }
+    AbiRange(const AbiRange &) = delete;
+    AbiRange &operator=(const AbiRange &) = delete;
+};
+#define LIGATE_ABI_RANGE() const ::ligate::AbiRange ligate_abi_range_(__func__)
 
 // ---------------------------------------------------------------------------------------------
 // Errors

@@ -119,6 +119,7 @@ int grid_desc_check(const dock_grid_desc *g) { return check_desc(g); }
 using namespace ligate;
 
 extern "C" int dock_grid_bytes(const dock_grid_desc *g, size_t *bytes) {
+    LIGATE_ABI_RANGE();
     int rc = check_desc(g);
     if (rc) return rc;
     LIGATE_REQUIRE(bytes != nullptr, DOCK_ERR_INVALID_ARG, "bytes is NULL");
@@ -129,6 +130,7 @@ extern "C" int dock_grid_bytes(const dock_grid_desc *g, size_t *bytes) {
 extern "C" int dock_build_grids(const dock_grid_desc *g, const float *d_prot_xyz, const int32_t *d_prot_type,
                                 int32_t n_prot, const dock_type_param *h_params, const dock_potential *pot,
                                 float *d_grids, void *stream) {
+    LIGATE_ABI_RANGE();
     int rc = check_desc(g);
     if (rc) return rc;
     LIGATE_REQUIRE(n_prot >= 0, DOCK_ERR_INVALID_ARG, "n_prot < 0");

@@ -278,6 +278,7 @@ extern "C" int dock_pack_ligands(const int32_t *d_atom_off, const float *d_xyz, 
                                  const int32_t *d_bond_off, const int32_t *d_bonds, const uint8_t *d_rot,
                                  int32_t n_lig, int64_t n_atoms_total, int32_t n_types, void *d_pack,
                                  size_t *pack_bytes, int32_t *d_status, void *stream) {
+    LIGATE_ABI_RANGE();
     LIGATE_REQUIRE(n_lig >= 0 && n_atoms_total >= 0 && n_atoms_total < (1ll << 31), DOCK_ERR_INVALID_ARG,
                    "bad library size (n_lig %d, n_atoms %lld)", n_lig, (long long)n_atoms_total);
     LIGATE_REQUIRE(n_types >= 1 && n_types <= DOCK_MAX_TYPES, DOCK_ERR_LIMIT, "n_types must be in [1, 32]");

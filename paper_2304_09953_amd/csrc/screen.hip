@@ -1463,6 +1463,7 @@ extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const
                            uint16_t *d_best_steps, float *d_start_scores, uint16_t *d_start_steps,
                            uint64_t *d_pose_count, void *d_ws,
                            size_t *ws_bytes, void *stream) {
+    LIGATE_ABI_RANGE();
     int rc = grid_desc_check(gd);
     if (rc) return rc;
     rc = check_search(sd);
@@ -1534,6 +1535,7 @@ extern "C" int dock_score_poses(const dock_grid_desc *gd, const float *d_grids, 
                                 int64_t n_atoms_total, const dock_search *sd, const int32_t *d_lig,
                                 const int32_t *d_start, const uint16_t *d_steps, int64_t n_poses, float *d_scores,
                                 void *stream) {
+    LIGATE_ABI_RANGE();
     int rc = grid_desc_check(gd);
     if (rc) return rc;
     rc = check_search(sd);
@@ -1569,6 +1571,7 @@ extern "C" int dock_rescore(const dock_grid_desc *gd, const float *d_grids, cons
                             float rmsd_min, int32_t *d_pose_start, uint16_t *d_pose_steps, float *d_pose_score,
                             float *d_pose_rescore, float *d_best_rescore, int32_t *d_best_pose, double *d_pose_xyz,
                             void *stream) {
+    LIGATE_ABI_RANGE();
     int rc = grid_desc_check(gd);
     if (rc) return rc;
     rc = check_search(sd);

@@ -143,6 +143,7 @@ using namespace ligate;
 
 extern "C" int dock_topk(const float *d_scores, const int32_t *d_ids, int64_t n, int32_t k, float *d_out_scores,
                          int32_t *d_out_ids, void *d_ws, size_t *ws_bytes, void *stream) {
+    LIGATE_ABI_RANGE();
     LIGATE_REQUIRE(n >= 1 && n < (1ll << 31), DOCK_ERR_INVALID_ARG, "n must be in [1, 2^31)");
     LIGATE_REQUIRE(k >= 1 && k <= n, DOCK_ERR_INVALID_ARG, "k must be in [1, n]");
     LIGATE_REQUIRE(ws_bytes != nullptr, DOCK_ERR_INVALID_ARG, "ws_bytes is NULL");
@@ -189,6 +190,7 @@ __global__ void k_merge_pockets(const float *__restrict__ scores, int n_pockets,
 
 extern "C" int dock_merge_pockets(const float *d_scores, int32_t n_pockets, int64_t n, float *d_best,
                                   int32_t *d_pocket, void *stream) {
+    LIGATE_ABI_RANGE();
     LIGATE_REQUIRE(n_pockets >= 1 && n_pockets <= 1024, DOCK_ERR_INVALID_ARG, "n_pockets must be in [1, 1024]");
     LIGATE_REQUIRE(n >= 1 && n < (1ll << 31), DOCK_ERR_INVALID_ARG, "n must be in [1, 2^31)");
     LIGATE_REQUIRE(d_scores && d_best && d_pocket, DOCK_ERR_INVALID_ARG, "NULL array");

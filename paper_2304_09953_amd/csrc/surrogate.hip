@@ -359,6 +359,7 @@ static void run_forward(const surr_model *m, const Layout &L, const uint16_t *x,
 using namespace ligate;
 
 extern "C" int surr_param_count(int32_t d_in, int32_t h1, int32_t h2, int64_t *n_master, int64_t *n_bf16) {
+    LIGATE_ABI_RANGE();
     LIGATE_REQUIRE(d_in > 0 && h1 > 0 && h2 > 0 && n_master && n_bf16, DOCK_ERR_INVALID_ARG, "bad widths");
     const Layout L = Layout::of(d_in, h1, h2);
     *n_master = L.n_master;
@@ -369,6 +370,7 @@ extern "C" int surr_param_count(int32_t d_in, int32_t h1, int32_t h2, int64_t *n
 extern "C" int surr_features(const int32_t *d_atom_off, const float *d_xyz, const uint8_t *d_type, const void *d_pack,
                              int32_t n_lig, int64_t n_atoms_total, int32_t n_types, const float *d_mean,
                              const float *d_istd, float *d_feat, uint16_t *d_feat_bf16, void *stream) {
+    LIGATE_ABI_RANGE();
     LIGATE_REQUIRE(n_lig >= 0 && n_atoms_total >= 0 && n_atoms_total < (1ll << 31), DOCK_ERR_INVALID_ARG,
                    "bad library size");
     LIGATE_REQUIRE(n_types >= 1 && n_types <= SURR_MAX_TYPES, DOCK_ERR_LIMIT, "features need n_types <= 16");
@@ -384,6 +386,7 @@ extern "C" int surr_features(const int32_t *d_atom_off, const float *d_xyz, cons
 
 extern "C" int surr_feature_stats(const float *d_feat, int64_t n_rows, float *d_mean, float *d_istd, void *d_ws,
                                   size_t *ws_bytes, void *stream) {
+    LIGATE_ABI_RANGE();
     LIGATE_REQUIRE(n_rows >= 1 && ws_bytes, DOCK_ERR_INVALID_ARG, "bad arguments");
     const int64_t chunks = (n_rows + kStatRows - 1) / kStatRows;
     const size_t need = al(sizeof(double) * 2 * SURR_FEATURES * (size_t)chunks);
@@ -402,6 +405,7 @@ extern "C" int surr_feature_stats(const float *d_feat, int64_t n_rows, float *d_
 }
 
 extern "C" int surr_cast(const surr_model *m, void *stream) {
+    LIGATE_ABI_RANGE();
     int rc = check_model(m, false);
     if (rc) return rc;
     const Layout L = Layout::of(m->d_in, m->h1, m->h2);
@@ -413,6 +417,7 @@ extern "C" int surr_cast(const surr_model *m, void *stream) {
 
 extern "C" int surr_forward(const surr_model *m, const uint16_t *d_x, int32_t batch, float *d_y, void *d_ws,
                             size_t *ws_bytes, void *stream) {
+    LIGATE_ABI_RANGE();
     int rc = check_model(m, false);
     if (rc) return rc;
     LIGATE_REQUIRE(batch >= 1 && ws_bytes, DOCK_ERR_INVALID_ARG, "bad batch");
@@ -434,6 +439,7 @@ extern "C" int surr_forward(const surr_model *m, const uint16_t *d_x, int32_t ba
 
 extern "C" int surr_backward(const surr_model *m, const uint16_t *d_x, const float *d_t, int32_t batch, float *d_loss,
                              void *d_ws, size_t *ws_bytes, void *stream) {
+    LIGATE_ABI_RANGE();
     int rc = check_model(m, true);
     if (rc) return rc;
     LIGATE_REQUIRE(batch >= 32 && batch % 32 == 0 && ws_bytes, DOCK_ERR_INVALID_ARG,
@@ -484,6 +490,7 @@ extern "C" int surr_backward(const surr_model *m, const uint16_t *d_x, const flo
 
 extern "C" int surr_adam(const surr_model *m, float lr, float beta1, float beta2, float eps, int32_t step,
                          void *stream) {
+    LIGATE_ABI_RANGE();
     int rc = check_model(m, true);
     if (rc) return rc;
     LIGATE_REQUIRE(step >= 1 && lr > 0.0f && beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f &&
@@ -517,6 +524,7 @@ __global__ void k_gather_f32(const float *__restrict__ src, const int32_t *__res
 
 extern "C" int surr_gather(const uint16_t *d_x, const float *d_t, const int32_t *d_idx, int64_t n_idx, int32_t row,
                            uint16_t *d_x_out, float *d_t_out, void *stream) {
+    LIGATE_ABI_RANGE();
     LIGATE_REQUIRE(n_idx >= 0 && row >= 1 && d_idx, DOCK_ERR_INVALID_ARG, "bad gather arguments");
     LIGATE_REQUIRE((d_x == nullptr) == (d_x_out == nullptr) && (d_t == nullptr) == (d_t_out == nullptr),
                    DOCK_ERR_INVALID_ARG, "inputs and outputs go together");
