@@ -723,12 +723,15 @@ def main():
         "l1_to_l2_bytes_per_s": c["l1_to_l2_bytes_per_launch"] / t_screen if c else None,
         "l2_read_peak_bytes_per_s": l2_peak,
         "frac": c["l1_to_l2_bytes_per_launch"] / t_screen / l2_peak if c else None,
+        "algorithmic_frac": BYTES_PER_LOOKUP * lookups / t_screen / l2_peak,
         "l2_hit_rate": c["l2_hit_rate"] if c else None,
         "hbm_side_bytes_per_s": c["hbm_bytes_per_launch"] / t_screen if c else None,
         "hbm_side_frac": c["hbm_bytes_per_launch"] / t_screen / 8e12 if c else None,
         "valu_busy": c["valu_busy"] if c else None,
-        "note": "L1-to-L2 request bytes (rocprofv3, per launch) over the measured L2-resident read peak; "
-                "HBM side = FETCH_SIZE + WRITE_SIZE (Infinity Cache hits included) over 8 TB/s",
+        "note": "frac: L1-to-L2 request bytes (rocprofv3, per launch) over the measured L2-resident read peak; "
+                "algorithmic_frac: the lookups' 32 B each over the same peak (the bytes the lanes gather, "
+                "L1 hits included); HBM side = FETCH_SIZE + WRITE_SIZE (Infinity Cache hits included) "
+                "over 8 TB/s",
     }
 
     out = {
