@@ -763,6 +763,11 @@ def main():
                      "algorithmic_flop_per_launch": flop, "lookups_per_launch": lookups,
                      "gather_bytes_per_s": BYTES_PER_LOOKUP * lookups / (screen_ms * 1e-3)},
         "gather_roofline": gather,
+        # the paper's only throughput figure, as context (not comparable: its ligands, sites, search
+        # and scoring differ, and the machines are not named)
+        "paper_context": {"ligands_per_s": 7e10 / (60 * 3600.0),
+                          "what": "campaign total: more than 7e10 ligands against 15 sites in 60 h (paper, section 2)",
+                          "hardware": "two supercomputers, 81 PFLOP/s combined peak, machines and precision not stated"},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, ligs, args.cpu_seconds)
