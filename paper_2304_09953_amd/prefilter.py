@@ -120,6 +120,26 @@ class Surrogate:
         """Mean of the members' outputs (z-scores of the best docking score) for BF16 features."""
         return np.mean([m.predict(xb).cpu().numpy().astype(np.float64) for m in self.models], axis=0)
 
+    def save(self, path: str) -> None:
+        """Writes the trained filter to an .npz: each member's FP32 master weights and layer sizes, the
+        feature normalisation and the score scale (no optimiser state; Model.state holds that)."""
+        m0 = self.models[0]
+        arrays = {f"member_{i}": m.master.cpu().numpy() for i, m in enumerate(self.models)}
+        np.savez(path, **arrays, dims=np.array([m0.d_in, m0.h1, m0.h2, len(self.models)], np.int64),
+                 mean=self.mean.cpu().numpy(), istd=self.istd.cpu().numpy(),
+                 y=np.array([self.y_mean, self.y_std], np.float64),
+                 metrics=np.array(json.dumps(self.metrics, default=float)))
+
+    @classmethod
+    def load(cls, path: str, device="cuda") -> "Surrogate":
+        """Reads a filter written by save(); its predictions equal the saved filter's bit for bit."""
+        with np.load(path, allow_pickle=False) as z:
+            d_in, h1, h2, n = (int(v) for v in z["dims"])
+            models = [SG.Model(z[f"member_{i}"], d_in, h1, h2, device=device) for i in range(n)]
+            y_mean, y_std = (float(v) for v in z["y"])
+            return cls(models, torch.as_tensor(z["mean"]).to(device), torch.as_tensor(z["istd"]).to(device),
+                       y_mean, y_std, metrics=json.loads(str(z["metrics"])))
+
     def fingerprint(self) -> str:
         """Hash of the members' weights and the input normalisation (identifies a trained filter)."""
         h = hashlib.sha256()

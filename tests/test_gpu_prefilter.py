@@ -101,3 +101,15 @@ def test_training_resumes_after_a_failure(trained, tmp_path, monkeypatch):
     assert res.metrics["loss_first_epoch"] == ref.metrics["loss_first_epoch"]
     assert res.metrics["loss_last_epoch"] == ref.metrics["loss_last_epoch"]
     assert np.array_equal(res.holdout_pred, ref.holdout_pred)
+
+
+def test_saved_filter_predicts_like_the_trained_one(trained, tmp_path):
+    P, PF, W, dp, ds, ligs, sur = trained
+    path = str(tmp_path / "filter.npz")
+    sur.save(path)
+    back = PF.Surrogate.load(path)
+    assert back.fingerprint() == sur.fingerprint()
+    lib = P.DeviceLibrary(I.make_ligands(500, W.dist, W.n_types, stream="sample"))
+    say("saved and reloaded filter: predictions of 500 ligands")
+    assert np.array_equal(back.predict_library(lib), sur.predict_library(lib))
+    assert back.metrics["best_epochs"] == sur.metrics["best_epochs"]
