@@ -119,3 +119,19 @@ def test_zero_restarts_repeat_the_plain_search(env):
         assert np.array_equal(r["start_steps"][:, k * QT:(k + 1) * QT], base["start_steps"])
     for key in ("score", "start", "steps"):
         assert np.array_equal(np.asarray(r[key]), np.asarray(base[key])), key
+
+
+@pytest.mark.parametrize("boundary", [0, 1])
+def test_budget_variants_are_layout_independent(env, boundary):
+    # selection, passes and restarts run through the same lookups in both grid layouts, so the two
+    # give the same screen bit for bit, under either boundary mode
+    P, W, pocket, G, ligs, _ = env
+    variants = [dict(sweep_top=16, passes=2), dict(restarts=2, init_steps=I.restart_steps(2, W.search.n_steps))]
+    for v in variants:
+        srch = dataclasses.replace(W.search, **v)
+        runs = []
+        for layout in (0, 1):
+            say(f"pocket48-lib100 subset of 20: {sorted(v)}, boundary {boundary}, layout {layout}")
+            runs.append(_screen(P, P.DevicePocket(pocket, boundary=boundary, layout=layout), ligs, srch))
+        for key in ("score", "start", "steps", "poses", "finals", "start_steps"):
+            assert np.array_equal(runs[0][key], runs[1][key]), (v, key)
