@@ -79,3 +79,22 @@ def test_rescore_matches_oracle(env, n_keep, rmsd_min, top, passes, restarts):
             assert np.array_equal(kept, live)
     say(f"threshold flips: {flips}")
     assert flips <= 1
+
+
+def test_rescore_is_layout_independent(env):
+    # the pose replay runs the screen's lookups, which give the same values in both grid layouts
+    P, W, pocket, ligs, _, lib = env
+    ds = P.DeviceSearch(W.search)
+    n, QT = ligs.n_lig, W.search.n_searched
+    outs = []
+    for layout in (0, 1):
+        say(f"rescore: keep 8, rmsd_min 1.0, layout {layout}")
+        dp = P.DevicePocket(pocket, layout=layout)
+        scr = P.screen(dp, lib, ds, start_scores=True)
+        res = P.rescore(dp, lib, ds, scr.start_scores.view(n, QT), 8, 1.0, want_xyz=True)
+        torch.cuda.synchronize()
+        outs.append({k: getattr(res, k).cpu() for k in ("pose_start", "pose_steps", "pose_score", "pose_rescore",
+                                                         "pose_xyz", "best_rescore", "best_pose")})
+    for k in outs[0]:
+        assert torch.equal(outs[0][k], outs[1][k]) or (
+            outs[0][k].dtype.is_floating_point and torch.equal(outs[0][k].nan_to_num(7.0), outs[1][k].nan_to_num(7.0))), k
