@@ -74,6 +74,37 @@ def test_graph_replays_match_eager_runs(env, uneven):
         _ = torch.ones(1000, device="cuda").sum()  # unrelated eager work between replays
 
 
+@pytest.mark.parametrize("budget", ["top16-passes2", "restarts2"])
+def test_graph_replays_of_budget_searches_match_eager(env, uneven, budget):
+    # start selection (its own kernel and workspace) and restarts inside captured chunks
+    import dataclasses
+    P, Bt = env
+    W, ligs = uneven
+    pocket = W.pockets[0]
+    v = dict(sweep_top=16, passes=2) if budget == "top16-passes2" else \
+        dict(restarts=2, init_steps=I.restart_steps(2, W.search.n_steps))
+    srch = I.search_for(pocket, dataclasses.replace(W.search, **v))
+    dp = P.DevicePocket(pocket)
+    sub = ligs.subset(np.arange(64))
+    say(f"{budget}: eager screen of 64 ligands")
+    r = P.screen(dp, P.DeviceLibrary(sub), P.DeviceSearch(srch))
+    torch.cuda.synchronize()
+    eager = r.best_score.cpu().numpy()
+    shape = Bt.chunk_shape_for(sub, np.arange(64), 64)
+    graph = Bt.ChunkPipeline(dp, srch, shape, sub.n_types, 64, use_graph=True)
+    for rep in range(2):
+        say(f"{budget}: graph replay {rep}")
+        graph.reset()
+        graph.load(sub, sub.ids.astype(np.int32))
+        graph.run()
+        torch.cuda.synchronize()
+        assert np.array_equal(graph.scores.cpu().numpy()[64:128], eager)  # the chunk's per-ligand best
+        ref_s, ref_i = oracle.topk(eager, 64, sub.ids)
+        assert np.array_equal(graph.ids.cpu().numpy()[:64], ref_i.astype(np.int32))
+        assert np.array_equal(graph.scores.cpu().numpy()[:64], ref_s.astype(np.float32))
+        _ = torch.ones(1000, device="cuda").sum()  # unrelated eager work between replays
+
+
 def test_large_pocket_parity_sample(env, uneven):
     P, Bt = env
     W, ligs = uneven
