@@ -321,7 +321,7 @@ def rescore_bench(args):
 
 
 def knob_tuning(args):
-    """Bayesian tuning of (Q, T, S, passes, sweep_top) for the cheapest screen whose top 1 % keeps
+    """Bayesian tuning of (Q, T, S, passes, sweep_top, restarts) for the cheapest screen whose top 1 % keeps
     args.knob_target of the reference search's top 1 % on a sample library; compared with random search
     at the same number of screens and with every configuration of the grid."""
     import dataclasses
@@ -360,8 +360,10 @@ def knob_tuning(args):
     def evaluate(cfg):
         key = tuple(sorted(cfg.items()))
         if key not in cache:
+            R = cfg.get("restarts", 0)
             srch = dataclasses.replace(I.make_search(cfg["n_quat"], cfg["n_trans"], cfg["n_steps"], 4.0, pocket.center),
-                                       sweep_top=cfg["sweep_top"], passes=cfg["passes"])
+                                       sweep_top=cfg["sweep_top"], passes=cfg["passes"], restarts=R,
+                                       init_steps=I.restart_steps(R, cfg["n_steps"]) if R else None)
             t, best = screen(srch)
             top = set(ids[np.lexsort((ids, best[ok]))[:k]].tolist())
             cache[key] = (t / n_lig * 1e6, len(top & top_ref) / k)  # seconds per 1M ligands, recall
@@ -370,7 +372,11 @@ def knob_tuning(args):
     target = args.knob_target
     bo = K.optimize(evaluate, target, n_init=6, n_iter=args.knob_evals - 6, seed=0, log=log)
     rnd = [K.random_search(evaluate, target, args.knob_evals, seed=s)["best"] for s in range(5)]
-    every = [{"cfg": c, "cost": evaluate(c)[0], "recall": evaluate(c)[1]} for c in K.grid()]
+    every = []
+    for i, c in enumerate(K.grid()):
+        every.append({"cfg": c, "cost": evaluate(c)[0], "recall": evaluate(c)[1]})
+        if (i + 1) % 50 == 0:
+            log(f"grid: {i + 1} configurations screened")
     truth = K.best_feasible(every, target)
     front = sorted(every, key=lambda h: h["cost"])
     pareto, best_r = [], -1.0

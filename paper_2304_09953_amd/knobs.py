@@ -3,7 +3,8 @@
 The paper tunes the docking engine's quality/performance knobs with a Bayesian optimiser (§3.3,
 LiGen autotuning: a method aimed at the cheapest configuration of a recurring, constrained job).
 Here the knobs are the number of quaternions Q, of translations T, of torsion steps S, of greedy
-passes and of swept starts (sweep_top); the constraint is the recall of a reference ranking's top
+passes, of swept starts (sweep_top) and of torsion restarts per rigid start (which the search runs
+only over every start, so they exclude sweep_top); the constraint is the recall of a reference ranking's top
 1 % on a sample library, the cost the screen's time per ligand.  The model is a Gaussian process
 per objective (log time, recall) over the knobs scaled to [0, 1] on a log2 axis; the next
 configuration maximises expected improvement of the time weighted by the probability that the
@@ -18,17 +19,20 @@ import math
 import numpy as np
 
 SPACE = {"n_quat": (32, 64, 128, 256), "n_trans": (8, 16, 32), "n_steps": (64, 128, 256), "passes": (1, 2),
-         "sweep_top": (0, 64, 256, 1024)}
+         "sweep_top": (0, 64, 256, 1024), "restarts": (0, 1, 2)}
 
 
 def grid(space: dict = SPACE) -> list[dict]:
-    """Every combination; a sweep_top reaching Q*T means every start, so it collapses onto 0."""
+    """Every valid combination; a sweep_top reaching Q*T means every start, so it collapses onto 0, and
+    restarts go only with every start (sweep_top 0)."""
     out, seen = [], set()
     keys = list(space)
     for vals in itertools.product(*(space[k] for k in keys)):
         c = dict(zip(keys, vals))
         if c.get("sweep_top", 0) >= c["n_quat"] * c["n_trans"]:
             c["sweep_top"] = 0
+        if c.get("sweep_top", 0) and c.get("restarts", 0):
+            continue
         t = tuple(c[k] for k in keys)
         if t not in seen:
             seen.add(t)
@@ -38,13 +42,16 @@ def grid(space: dict = SPACE) -> list[dict]:
 
 def encode(cfgs: list[dict], space: dict = SPACE) -> np.ndarray:
     """Knob values on a log2 axis scaled to [0, 1] per knob (sweep_top 0, i.e. every start, sits at the
-    top of its axis, beyond the largest K)."""
+    top of its axis, beyond the largest K; restarts R as 1 + R)."""
     cols = []
     for k, vals in space.items():
         if k == "sweep_top":
             top = max(vals) * 4
             f = lambda v: math.log2(v if v > 0 else top)  # noqa: E731
             lo, hi = math.log2(min(v for v in vals if v > 0)), math.log2(top)
+        elif k == "restarts":  # searched start sets 1 + R on the log2 axis
+            f = lambda v: math.log2(1 + v)  # noqa: E731
+            lo, hi = math.log2(1 + min(vals)), math.log2(1 + max(vals))
         else:
             f, lo, hi = math.log2, math.log2(min(vals)), math.log2(max(vals))
         cols.append([(f(c[k]) - lo) / (hi - lo) if hi > lo else 0.0 for c in cfgs])

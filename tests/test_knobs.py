@@ -5,20 +5,24 @@ from paper_2304_09953_amd import knobs as K
 
 
 def _synthetic(cfg):
-    # cost grows with the work; recall saturates with the work, more with passes and every start
+    # cost grows with the work; recall saturates with the work, more with passes, restarts and every start
     work = cfg["n_quat"] * cfg["n_trans"] * cfg["n_steps"] / (32 * 8 * 64)
     swept = 1.0 if cfg["sweep_top"] == 0 else min(1.0, cfg["sweep_top"] / (cfg["n_quat"] * cfg["n_trans"]))
-    cost = work * (0.1 + 0.9 * swept) * cfg["passes"] ** 0.8
-    recall = 1 - np.exp(-0.9 * np.log2(work * 2) * (0.5 + 0.5 * swept) * (1 + 0.15 * (cfg["passes"] - 1)))
+    r = cfg.get("restarts", 0)
+    cost = work * (0.1 + 0.9 * swept) * cfg["passes"] ** 0.8 * (1 + r)
+    recall = 1 - np.exp(-0.9 * np.log2(work * 2) * (0.5 + 0.5 * swept) * (1 + 0.15 * (cfg["passes"] - 1))
+                        * (1 + 0.1 * r))
     return cost, recall
 
 
-def test_grid_collapses_selection_that_covers_every_start():
+def test_grid_collapses_selection_and_excludes_restarts_with_it():
     g = K.grid()
     assert len(g) == len({tuple(c.values()) for c in g})
     assert all(c["sweep_top"] < c["n_quat"] * c["n_trans"] for c in g)
+    assert not any(c["sweep_top"] and c["restarts"] for c in g)  # restarts only over every start
+    assert any(c["restarts"] for c in g)
     X = K.encode(g)
-    assert X.shape == (len(g), 5) and X.min() >= 0 and X.max() <= 1
+    assert X.shape == (len(g), len(K.SPACE)) and X.min() >= 0 and X.max() <= 1
 
 
 def test_gp_interpolates_its_data():
