@@ -760,7 +760,7 @@ def main():
         "config": {"workload": (W.name if n_lig == W.n_lig else f"first {n_lig} ligands of " + W.name)
                    + "; top-1000",
                    "n_lig": n_lig, "grid": "96^3x16", "grid_layout": args.layout, "search": "Q256xT32xS256",
-                   "top_k": k},
+                   "top_k": k, "seed": I.BASE_SEED},
         "poses_per_sec": poses * args.steps / dt,
         "screen_ms": screen_ms,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_NONPACKED / 1e12,
