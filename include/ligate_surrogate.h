@@ -53,7 +53,10 @@ int surr_param_count(int32_t d_in, int32_t h1, int32_t h2, int64_t *n_master, in
  * type-t atoms, slots 1..30 = ordered-pair counts of distances from type-t atoms to every other
  * atom in 0.5 A bins on [1.25, 16.25) A (ends folded in; the bin is decided on the FP32 squared
  * distance against the exact squared edges), slot 31 = rotatable-bond count; then log1p.  If
- * d_mean and d_istd are given, (f - mean) * istd.  Ligands whose status is not OK get zeros.
+ * d_mean and d_istd are given, (f - mean) * istd.  Ligands whose status is not OK get zeros,
+ * and so does a ligand holding an atom type >= 16 (a pack built with more types than the
+ * features have rows).  The bin of a pair within about 1e-6 A of an inner edge is decided by
+ * FP32 rounding and may be either neighbour.
  * Outputs (either may be NULL): d_feat [n_lig][512] FP32, d_feat_bf16 [n_lig][512] BF16 bits.
  * Requires n_types <= 16.
  */

@@ -10,16 +10,22 @@ that only the most promising fraction is docked.
 * Features (512 per ligand, 16 rows of 32): row t holds the number of type-t atoms, a 30-bin
   histogram of the distances from type-t atoms to every other atom (0.5 A bins on [1.25, 16.25) A,
   values outside folded into the end bins, so the 1.5 A bond length sits mid-bin; ordered pairs,
-  i.e. the per-type-pair histograms
-  summed over the partner type) and the rotatable-bond count; then log1p.  The bin of a pair is
-  decided on its squared distance, computed in FP32 from the input coordinates
-  (dx*dx + dy*dy + dz*dz, each product and sum rounded), against the exactly representable
-  squared bin edges: the same decision the kernel takes.
+  i.e. the per-type-pair histograms summed over the partner type) and the rotatable-bond count;
+  then log1p.  Distances are Euclidean norms in FP64 of the FP32 input coordinates (widened
+  exactly); a distance equal to an inner edge belongs to the bin above it.  A pair lying within
+  EDGE_FLAG (1e-5 A) of an inner edge is reported per row by raw_features_flagged: any
+  implementation that rounds the distance differently (FP32, or a squared-distance comparison)
+  may put such a pair in either neighbouring bin, and it is the only kind of pair that may
+  differ.
 * Network: y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3, 512 -> 1024 -> 1024 -> 1.  Weights are
   BF16 copies (round to nearest even) of FP32 master weights; the input and both hidden layers
   are stored in BF16; sums are exact here (FP64).  Loss: mean squared error.
-* Backward: dy = 2 (y - t) / B; hidden-layer gradients are stored in BF16 like the activations;
-  weight gradients are FP64 here.
+* Backward: dy = 2 (y - t) / B.  The gradients at the two hidden layers are operands of the
+  backward products (they multiply the stored activations to give the weight gradients, and W2
+  to give the gradient one layer down), and every operand of a BF16 product is a BF16 value, so
+  they are rounded to BF16 like the forward operands.  Weight gradients are FP64 here.  A pin
+  compares this gradient with the exact chain rule (grad_exact) of the same network evaluated on
+  BF16-rounded weights and inputs: they differ only by these roundings.
 * Adam (Kingma and Ba, 2015) with bias correction, no weight decay.
 """
 from __future__ import annotations
@@ -51,29 +57,40 @@ def bf16_bits(x) -> np.ndarray:
 # Features
 # ------------------------------------------------------------------------------------------------
 
-def raw_features(ligs, status=None) -> np.ndarray:
-    """Per-type counts, distance histograms and rotatable count (before log1p); [n_lig, 512].
-    Ligands whose status is not OK get all-zero rows."""
+EDGE_FLAG = 1e-5  # Angstrom
+
+
+def raw_features_flagged(ligs, status=None):
+    """Per-type counts, distance histograms and rotatable count (before log1p), [n_lig, 512], and
+    per (ligand, row) the number of pairs within EDGE_FLAG of an inner bin edge, [n_lig, 16].
+    Ligands whose status is not OK, or that hold an atom type >= 16, get all-zero rows."""
     out = np.zeros((ligs.n_lig, N_ROWS, N_SLOTS), dtype=np.float64)
-    edges2 = (BIN_LO + BIN_W * np.arange(1, N_BINS)) ** 2  # inner edges 1.75 .. 15.75, squared (exact)
+    near = np.zeros((ligs.n_lig, N_ROWS), dtype=np.int64)
+    inner = BIN_LO + BIN_W * np.arange(1, N_BINS)  # 1.75 .. 15.75 A
     n_rot = ligs.n_rot
     for l in range(ligs.n_lig):
         if status is not None and status[l] != 0:
             continue
         x, t, _, _ = ligs.ligand(l)
-        x = x.astype(np.float32)
+        x = x.astype(np.float64)
         t = t.astype(np.int64)
         n = len(t)
-        out[l, :, 0] = np.bincount(t, minlength=N_ROWS)[:N_ROWS]
+        if n == 0 or t.max() >= N_ROWS:
+            continue  # a type without a row: the ligand is not representable, zero features
+        out[l, :, 0] = np.bincount(t, minlength=N_ROWS)
         if n > 1:
-            d = x[:, None, :] - x[None, :, :]          # FP32 differences
-            d2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
-            assert d2.dtype == np.float32
-            ii, jj = np.nonzero(~np.eye(n, dtype=bool))
-            b = np.searchsorted(edges2, d2[ii, jj].astype(np.float64), side="right")
+            ii, jj = np.nonzero(~np.eye(n, dtype=bool))  # ordered pairs i != j
+            d = np.sqrt(np.sum((x[ii] - x[jj]) ** 2, axis=1))
+            b = np.searchsorted(inner, d, side="right")  # 0 below 1.75 A ... 29 from 15.75 A
             np.add.at(out[l], (t[ii], 1 + b), 1.0)
+            flag = np.min(np.abs(d[:, None] - inner[None, :]), axis=1) < EDGE_FLAG
+            np.add.at(near[l], t[ii], flag.astype(np.int64))
         out[l, :, N_SLOTS - 1] = n_rot[l]
-    return out.reshape(ligs.n_lig, N_ROWS * N_SLOTS)
+    return out.reshape(ligs.n_lig, N_ROWS * N_SLOTS), near
+
+
+def raw_features(ligs, status=None) -> np.ndarray:
+    return raw_features_flagged(ligs, status)[0]
 
 
 def features(ligs, status=None) -> np.ndarray:

@@ -34,7 +34,14 @@ __global__ __launch_bounds__(64) void k_features(const int32_t *__restrict__ ato
     __shared__ int cnt[kRows * kSlots];
     const int l = blockIdx.x, lane = lane_id();
     const LigDesc d = pk.desc[l];
-    const bool ok = d.status == DOCK_LIG_OK;
+    bool ok = d.status == DOCK_LIG_OK;
+    if (ok) {
+        // the histogram has one row per type below kRows: a ligand with any other type (a pack
+        // built with more types) is not representable and gets zero features
+        bool bad = false;
+        for (int i = lane; i < d.n; i += kWave) bad |= type[atom_off[l] + i] >= kRows;
+        ok = __ballot(bad) == 0ull;
+    }
     for (int f = lane; f < kRows * kSlots; f += kWave) cnt[f] = 0;
     wave_sync();
     if (ok) {

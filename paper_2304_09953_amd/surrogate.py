@@ -49,14 +49,16 @@ def _lib():
 _p, _s, _check = dock._ptr, dock._stream, dock._check
 
 
-def features(lib_dev, mean=None, istd=None, f32: bool = True, bf16: bool = True, stream=None):
-    """Features of a DeviceLibrary: (FP32 [n, 512] or None, BF16 bits as int16 [n, 512] or None)."""
+def features(lib_dev, mean=None, istd=None, f32: bool = True, bf16: bool = True, stream=None, n_types=None):
+    """Features of a DeviceLibrary: (FP32 [n, 512] or None, BF16 bits as int16 [n, 512] or None).
+    n_types: the type count stated to the call (default: the library's)."""
     n = lib_dev.n_lig
     dev = lib_dev.pack.device
     F = torch.empty((n, FEATURES), dtype=torch.float32, device=dev) if f32 else None
     Fb = torch.empty((n, FEATURES), dtype=torch.int16, device=dev) if bf16 else None
     _check(_lib().surr_features(_p(lib_dev.atom_off), _p(lib_dev.xyz), _p(lib_dev.types), _p(lib_dev.pack), n,
-                                lib_dev.n_atoms, lib_dev.n_types, _p(mean), _p(istd), _p(F), _p(Fb), _s(stream)),
+                                lib_dev.n_atoms, lib_dev.n_types if n_types is None else n_types, _p(mean), _p(istd),
+                                _p(F), _p(Fb), _s(stream)),
            "surr_features")
     return F, Fb
 
