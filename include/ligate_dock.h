@@ -131,10 +131,15 @@ typedef struct {
     const int32_t *d_init_steps; /* [R][16] initial turns, device; NULL when R = 0 */
 } dock_search;
 
-/* Size in bytes of the grids for descriptor g. */
+/* Size in bytes of the grids for descriptor g (paper §2: the target is prepared once,
+ * before the library streams through). */
 int dock_grid_bytes(const dock_grid_desc *g, size_t *bytes);
 
 /*
+ * Paper §2: the workflow is structure based, scoring ligands against the 3D
+ * shape of the target's binding site; the receptor side of that score is
+ * tabulated once per pocket.  The functional form is this library's reading
+ * (the paper calls the docking score geometric and gives no formula).
  * Builds the receptor grids: for every ligand atom type t and node x,
  * G_t(x) = min(cap, sum_j E(t, type_j, |x - p_j|)) with
  * E(a, b, r) = sqrt(eps_a eps_b) [(r0/r')^12 - 2 (r0/r')^6] + coulomb_k q_a q_b / r',
@@ -146,6 +151,9 @@ int dock_build_grids(const dock_grid_desc *g, const float *d_prot_xyz, const int
                      const dock_type_param *h_params, const dock_potential *pot, float *d_grids, void *stream);
 
 /*
+ * Paper §2 (the first component computes each ligand's 3D atom placement for
+ * the later ones) and §3.3 (ligands are grouped by atom and rotatable-bond
+ * counts before the batched GPU kernels).
  * Packs a ligand library for the screen: centres each input conformer on its
  * unweighted centroid, stores coordinates as SoA, validates the bond tree,
  * finds the core (largest rigid fragment; ties to the one holding the lowest
@@ -166,6 +174,10 @@ int dock_pack_ligands(const int32_t *d_atom_off, const float *d_xyz, const uint8
                       void *stream);
 
 /*
+ * Paper §2: docking by a local search with multiple restarts, a geometric
+ * score per pose, and a ligand scored as its best pose; §3.3: a batch of
+ * ligand-protein pairs processed across the device at once, and the quality
+ * knobs (starts, steps, passes, restarts) of the search.
  * Docks every packed ligand: the searched starts (every rigid start, or the
  * sweep_top best, and their torsion restarts), each followed by the greedy
  * torsion passes; per ligand the lowest final score wins, ties to the lowest
@@ -191,10 +203,13 @@ int dock_screen(const dock_grid_desc *g, const float *d_grids, const void *d_pac
                 void *d_ws, size_t *ws_bytes, void *stream);
 
 /*
+ * Paper §2: the poses the docking generates are filtered, and the survivors are
+ * rescored with a function that adds physico-chemical information.
  * Pose filtering and rescoring after dock_screen.  For every packed ligand: the
  * n_keep searched starts with the lowest final scores in d_start_scores
- * (dock_screen's per-start output, [n_lig][n_quat*n_trans]; ties to the lower
- * start; +inf entries are not taken), in that order, each rerun with the
+ * (dock_screen's per-start output, [n_lig][N] with N = (1 + restarts) *
+ * n_quat*n_trans as in dock_screen; ties to the lower start; +inf entries are
+ * not taken), in that order, each rerun with the
  * screen's own code to recover its pose (its final equals the d_start_scores
  * entry bit for bit).  Walking them in that order, a pose is dropped when an
  * earlier kept pose lies within rmsd_min Angstrom of it (atom-by-atom RMSD, no
@@ -204,7 +219,7 @@ int dock_screen(const dock_grid_desc *g, const float *d_grids, const void *d_pac
  * (the grid potential with the distance-dependent dielectric 4r in place of 4,
  * no grid, no interpolation), plus the intra-ligand clash term.
  * g, d_grids, d_pack, n_lig, n_atoms_total, s: as for dock_screen (the same
- * search; n_quat*n_trans <= DOCK_MAX_TOP_STARTS).  Protein and potential: as
+ * search; N <= DOCK_MAX_TOP_STARTS).  Protein and potential: as
  * for dock_build_grids.  1 <= n_keep <= 16; rmsd_min >= 0 (Angstrom).
  * Outputs [n_lig][n_keep]: d_pose_start (-1 where there is no pose),
  * d_pose_steps [..][16] (total turns), d_pose_score (docking score, NaN where
@@ -222,6 +237,8 @@ int dock_rescore(const dock_grid_desc *g, const float *d_grids, const void *d_pa
                  int32_t *d_best_pose, double *d_pose_xyz, void *stream);
 
 /*
+ * Paper §2: the screened library is ranked and a small set of the strongest
+ * predicted binders is kept for the next stage.
  * Ranks scores: the k lowest, ties to the lower id, NaN ranked as +inf;
  * results in ascending order.  d_ids [n] (>= 0) or NULL for ids 0..n-1.
  * 1 <= k <= n < 2^31.  Workspace: query with d_ws == NULL.
@@ -230,6 +247,8 @@ int dock_topk(const float *d_scores, const int32_t *d_ids, int64_t n, int32_t k,
               int32_t *d_out_ids, void *d_ws, size_t *ws_bytes, void *stream);
 
 /*
+ * Paper §2: the molecules kept are those predicted to bind strongly to at least
+ * one binding site of the targets.
  * Ranking over several binding sites (a ligand is as good as its best site):
  * d_scores [n_pockets][n] holds, row by row, dock_screen's d_best_score of the
  * same n ligands against each pocket; NaN counts as +inf.  d_best [n] receives
@@ -241,6 +260,8 @@ int dock_merge_pockets(const float *d_scores, int32_t n_pockets, int64_t n, floa
                        void *stream);
 
 /*
+ * Paper §2: the geometric docking score of one pose, evaluated from scratch
+ * (tests and rescoring use it to check the search's incremental scores).
  * Scores explicit poses from scratch (no incremental bookkeeping): pose i is
  * ligand d_lig[i] placed at rigid start d_start[i], then torsion k (sweep
  * order) turned by step d_steps[i][k] for k < B.  d_steps is [n_poses][16].

@@ -799,19 +799,19 @@ struct ScreenArgs {
     PackView pk;
     const uint64_t *order;   // cost-sorted keys, ligand index in the low 32 bits
     uint64_t *best_key;      // [n_lig]
-    uint32_t *counter;
-    float *start_scores;     // optional [n_lig][QT]
+    unsigned long long *counter;  // 64-bit: n_items plus one exit pop per block may pass 2^31
+    float *start_scores;     // optional [n_lig][N]
     uint16_t *start_steps;   // optional [n_lig][QT][16]
     const uint32_t *sel;     // [n_lig][s.top] starts to search when s.top > 0
     int n_lig, P, bpl, nw;
     int64_t n_items;
 };
 
-__global__ void k_screen_init(uint64_t *best_key, int n_lig, uint32_t *counter, uint64_t *pose_count) {
+__global__ void k_screen_init(uint64_t *best_key, int n_lig, unsigned long long *counter, uint64_t *pose_count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_lig) best_key[i] = ~0ull;
     if (i == 0) {
-        *counter = 0u;
+        *counter = 0ull;
         if (pose_count) *pose_count = 0ull;
     }
 }
@@ -965,7 +965,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     extern __shared__ __align__(16) char smem[];
     LigLDS &L = *reinterpret_cast<LigLDS *>(smem);
     WaveLDS *Wv = reinterpret_cast<WaveLDS *>(smem + ((sizeof(LigLDS) + 15) & ~size_t(15)));
-    __shared__ int item_s;
+    __shared__ int64_t item_s;
     __shared__ uint64_t wbest_s[8];
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     WaveLDS &W = Wv[w];
@@ -974,7 +974,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const rsrc_t rs = grid_rsrc(A.g);
 
     for (;;) {
-        if (tid == 0) item_s = (int)atomicAdd(A.counter, 1u);
+        if (tid == 0) item_s = (int64_t)atomicAdd(A.counter, 1ull);
         __syncthreads();
         const int64_t item = item_s;
         if (item >= A.n_items) break;
@@ -1389,6 +1389,15 @@ static size_t al(size_t v) { return (v + 255) & ~size_t(255); }
 
 static size_t screen_lds(int nw) { return ((sizeof(LigLDS) + 15) & ~size_t(15)) + sizeof(WaveLDS) * (size_t)nw; }
 
+// Compute units of the calling thread's current device (queried per call: the device may change
+// between calls, and the query costs far less than a launch).
+static int default_cu_count() {
+    int dev = 0, cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    return cu > 0 ? cu : 256;
+}
+
 template <int APL, int BOUNDARY, int LAYOUT>
 static int launch_screen(const ScreenArgs &A, float *bs, int32_t *bp, uint16_t *bst, hipStream_t st) {
     if (A.s.top) {
@@ -1396,13 +1405,7 @@ static int launch_screen(const ScreenArgs &A, float *bs, int32_t *bp, uint16_t *
         hipLaunchKernelGGL((k_rigid_top<BOUNDARY, LAYOUT>), dim3((unsigned)A.n_lig), dim3(kTopBlock), lds, st, A,
                            const_cast<uint32_t *>(A.sel));
     }
-    static int cu = 0;
-    if (cu == 0) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
-        if (cu <= 0) cu = 256;
-    }
+    const int cu = default_cu_count();
     const size_t lds = screen_lds(A.nw);
     int per_cu = 0;
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_screen<APL, BOUNDARY, LAYOUT>),
@@ -1447,45 +1450,40 @@ static void replay_apl(int S, const PoseArgs &R, int n_lig, hipStream_t st) {
     return launch_pose_replay<16, BOUNDARY, LAYOUT>(R, n_lig, st);
 }
 
-static int default_cu_count() {
-    int dev = 0, cu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
-    return cu > 0 ? cu : 256;
-}
-
 }  // namespace ligate
 
 using namespace ligate;
 
-extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const void *d_pack, int32_t n_lig,
-                           int64_t n_atoms_total, const dock_search *sd, float *d_best_score, int32_t *d_best_start,
-                           uint16_t *d_best_steps, float *d_start_scores, uint16_t *d_start_steps,
-                           uint64_t *d_pose_count, void *d_ws,
-                           size_t *ws_bytes, void *stream) {
-    LIGATE_ABI_RANGE();
+namespace ligate {
+
+// Checks the screen's arguments that decide its workspace and returns the workspace size.
+static int screen_ws_need(const dock_grid_desc *gd, const dock_search *sd, int32_t n_lig, int64_t n_atoms_total,
+                          size_t *need) {
     int rc = grid_desc_check(gd);
     if (rc) return rc;
     rc = check_search(sd);
     if (rc) return rc;
     LIGATE_REQUIRE(n_lig >= 1 && n_atoms_total >= 0 && n_atoms_total < (1ll << 31), DOCK_ERR_INVALID_ARG,
                    "bad library size");
-    LIGATE_REQUIRE(ws_bytes != nullptr, DOCK_ERR_INVALID_ARG, "ws_bytes is NULL");
     const SearchC sc = make_search(sd, gd->spacing);
     const size_t sel_bytes = sc.top ? al(4 * (size_t)n_lig * (size_t)sc.top) : 0;
-    const size_t need = al(8 * (size_t)n_lig) + al(8 * (size_t)n_lig) + al(256) + sel_bytes + radix_sort_ws_bytes(n_lig);
-    if (d_ws == nullptr) {
-        *ws_bytes = need;
-        return DOCK_OK;
-    }
-    LIGATE_REQUIRE(*ws_bytes >= need, DOCK_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", *ws_bytes, need);
+    *need = al(8 * (size_t)n_lig) + al(8 * (size_t)n_lig) + al(256) + sel_bytes + radix_sort_ws_bytes(n_lig);
+    return DOCK_OK;
+}
+
+// Enqueues a screen whose arguments screen_ws_need accepted, with a workspace of at least that size.
+static int screen_enqueue(const dock_grid_desc *gd, const float *d_grids, const void *d_pack, int32_t n_lig,
+                          int64_t n_atoms_total, const dock_search *sd, float *d_best_score, int32_t *d_best_start,
+                          uint16_t *d_best_steps, float *d_start_scores, uint16_t *d_start_steps,
+                          uint64_t *d_pose_count, void *d_ws, hipStream_t st) {
     LIGATE_REQUIRE(d_grids && d_pack && d_best_score && d_best_start && d_best_steps, DOCK_ERR_INVALID_ARG,
                    "NULL array");
-    hipStream_t st = (hipStream_t)stream;
+    const SearchC sc = make_search(sd, gd->spacing);
+    const size_t sel_bytes = sc.top ? al(4 * (size_t)n_lig * (size_t)sc.top) : 0;
     char *w = (char *)d_ws;
     uint64_t *best_key = (uint64_t *)w;
     uint64_t *order = (uint64_t *)(w + al(8 * (size_t)n_lig));
-    uint32_t *counter = (uint32_t *)(w + 2 * al(8 * (size_t)n_lig));
+    unsigned long long *counter = (unsigned long long *)(w + 2 * al(8 * (size_t)n_lig));
     uint32_t *sel = sc.top ? (uint32_t *)(w + 2 * al(8 * (size_t)n_lig) + al(256)) : nullptr;
     void *rws = w + 2 * al(8 * (size_t)n_lig) + al(256) + sel_bytes;
 
@@ -1519,16 +1517,39 @@ extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const
     A.bpl = (n_searched + P - 1) / P;
     A.n_items = (int64_t)n_lig * A.bpl;
 
+    // the workspace is cleared by a kernel (best keys, the work counter, the pose count), never by
+    // a memset, so a captured or repeated call starts from zero
     const unsigned nb = (unsigned)((n_lig + 255) / 256);
     hipLaunchKernelGGL(k_screen_init, dim3(nb), dim3(256), 0, st, best_key, n_lig, counter, d_pose_count);
     // every rigid start is scored once when starts are selected, every searched start's first pose otherwise
     hipLaunchKernelGGL(k_screen_plan, dim3(nb), dim3(256), 0, st, A.pk.desc, n_lig, A.s.S, order, d_pose_count,
                        A.s.top ? A.s.QT : A.s.N, n_searched, A.s.passes);
-    rc = radix_sort_u64(order, n_lig, 32, 64, rws, st);
+    int rc = radix_sort_u64(order, n_lig, 32, 64, rws, st);
     if (rc) return rc;
     if (gd->layout == DOCK_LAYOUT_XY4)
         return dispatch_boundary<DOCK_LAYOUT_XY4>(gd->boundary, A.s.S, A, d_best_score, d_best_start, d_best_steps, st);
     return dispatch_boundary<DOCK_LAYOUT_LINEAR>(gd->boundary, A.s.S, A, d_best_score, d_best_start, d_best_steps, st);
+}
+
+}  // namespace ligate
+
+extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const void *d_pack, int32_t n_lig,
+                           int64_t n_atoms_total, const dock_search *sd, float *d_best_score, int32_t *d_best_start,
+                           uint16_t *d_best_steps, float *d_start_scores, uint16_t *d_start_steps,
+                           uint64_t *d_pose_count, void *d_ws,
+                           size_t *ws_bytes, void *stream) {
+    LIGATE_ABI_RANGE();
+    size_t need = 0;
+    int rc = screen_ws_need(gd, sd, n_lig, n_atoms_total, &need);
+    if (rc) return rc;
+    LIGATE_REQUIRE(ws_bytes != nullptr, DOCK_ERR_INVALID_ARG, "ws_bytes is NULL");
+    if (d_ws == nullptr) {
+        *ws_bytes = need;
+        return DOCK_OK;
+    }
+    LIGATE_REQUIRE(*ws_bytes >= need, DOCK_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", *ws_bytes, need);
+    return screen_enqueue(gd, d_grids, d_pack, n_lig, n_atoms_total, sd, d_best_score, d_best_start, d_best_steps,
+                          d_start_scores, d_start_steps, d_pose_count, d_ws, (hipStream_t)stream);
 }
 
 extern "C" int dock_score_poses(const dock_grid_desc *gd, const float *d_grids, const void *d_pack, int32_t n_lig,
@@ -1588,6 +1609,9 @@ extern "C" int dock_rescore(const dock_grid_desc *gd, const float *d_grids, cons
     LIGATE_REQUIRE(d_grids && d_pack && d_start_scores && d_pose_start && d_pose_steps && d_pose_score &&
                        d_pose_rescore && d_best_rescore && d_best_pose,
                    DOCK_ERR_INVALID_ARG, "NULL array");
+    // every argument is checked before the first launch: an error leaves the stream untouched
+    for (int t = 0; t < gd->n_types; ++t)
+        LIGATE_REQUIRE(h_params[t].eps >= 0.0, DOCK_ERR_INVALID_ARG, "eps of type %d is negative", t);
     hipStream_t st = (hipStream_t)stream;
     ScreenArgs A{};
     A.g = make_grid(gd, d_grids);
@@ -1611,7 +1635,6 @@ extern "C" int dock_rescore(const dock_grid_desc *gd, const float *d_grids, cons
     Q.n_prot = n_prot;
     for (int t = 0; t < DOCK_MAX_TYPES; ++t) {
         const dock_type_param p = t < gd->n_types ? h_params[t] : dock_type_param{1.0, 0.0, 0.0};
-        LIGATE_REQUIRE(p.eps >= 0.0, DOCK_ERR_INVALID_ARG, "eps of type %d is negative", t);
         Q.R[t] = p.R;
         Q.se[t] = sqrt(p.eps);
         Q.q[t] = p.q;

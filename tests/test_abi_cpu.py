@@ -160,6 +160,14 @@ def test_size_queries_and_argument_errors():
         assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(sr), None, None, None,
                                None, None, None, None, ctypes.byref(sz), None) == code, (R, init, top)
     assert "DOCK_MAX_RESTARTS 64" in open(os.path.join(ROOT, "include", "ligate_dock.h")).read()
+    # dock_rescore checks every argument, the type table included, before its first launch
+    T = 4
+    params = (dock.TypeParam * T)(*[dock.TypeParam(1.5, 0.1 if t < T - 1 else -0.1, 0.0) for t in range(T)])
+    pot = dock.Potential(10.0, 0.5, 83.0)
+    s8 = dock.SearchDesc(4, fake, 2, fake, 64, 2.5, 10.0, 0, 0)
+    assert lib.dock_rescore(ctypes.byref(_desc(dock)), fake, fake, 10, 300, ctypes.byref(s8), fake, fake, fake, 30,
+                            params, ctypes.byref(pot), 4, 1.0, fake, fake, fake, fake, fake, fake, None, None) == -1
+    assert b"eps of type 3" in lib.dock_last_error()
     assert lib.dock_merge_pockets(fake, 0, 10, fake, fake, None) == -1
     assert lib.dock_merge_pockets(fake, 2, 0, fake, fake, None) == -1
     assert lib.dock_merge_pockets(None, 2, 10, fake, fake, None) == -1

@@ -98,3 +98,29 @@ def test_rescore_is_layout_independent(env):
     for k in outs[0]:
         assert torch.equal(outs[0][k], outs[1][k]) or (
             outs[0][k].dtype.is_floating_point and torch.equal(outs[0][k].nan_to_num(7.0), outs[1][k].nan_to_num(7.0))), k
+
+
+def test_refused_rescore_enqueues_nothing(env):
+    """A negative well depth is an argument error: the call returns it before any launch, so the
+    outputs keep what they held."""
+    P, W, pocket, ligs, dp, lib = env
+    from paper_2304_09953_amd import dock
+    ds = P.DeviceSearch(W.search)
+    n, QT = ligs.n_lig, W.search.n_searched
+    say("rescore with a negative eps is refused before any launch")
+    scr = P.screen(dp, lib, ds, start_scores=True)
+    dev = dp.grids.device
+    sentinel = [torch.full((n, 4), -7, dtype=torch.int32, device=dev),
+                torch.full((n, 4, dock.MAX_TORSIONS), -7, dtype=torch.int16, device=dev),
+                torch.full((n, 4), -7.0, device=dev), torch.full((n, 4), -7.0, device=dev),
+                torch.full((n,), -7.0, device=dev), torch.full((n,), -7, dtype=torch.int32, device=dev)]
+    before = [t.clone() for t in sentinel]
+    pk = pocket.pocket
+    eps = np.array(pk.type_eps, dtype=np.float64).copy()
+    eps[-1] = -0.1
+    with pytest.raises(dock.DockError):
+        dock.rescore(dp.desc, dp.grids, lib.pack, n, lib.n_atoms, ds.desc, scr.start_scores.view(n, QT), dp.prot_xyz,
+                     dp.prot_type, pk.type_R, eps, pk.type_q, pk.cap, pk.r_min, pk.coulomb_k, 4, 1.0, *sentinel)
+    torch.cuda.synchronize()
+    for a, b in zip(sentinel, before):
+        assert torch.equal(a, b)
