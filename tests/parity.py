@@ -7,11 +7,13 @@ two implementations down different but equally valid paths.  The checks are:
   1. exactness  - the oracle rescores the GPU's reported pose (start, steps) in FP64 and
                   gets the GPU's score;
   2. validity   - replaying the GPU's path in FP64, every GPU decision is an argmin up to TAU;
-  3. optimality - the GPU's best is no worse than the oracle's when the oracle's winning
-                  path has no near-tie, and no better when the oracle's own path from the
-                  GPU's winning start has no near-tie;
+  3. optimality - the GPU's best is no worse than the oracle's wherever the GPU took the
+                  oracle's path from the oracle's winning start, and no better wherever the
+                  oracle took the GPU's path from the GPU's winning start; a ligand is excused
+                  only where the paths are shown to split at a near-tie, and such ligands
+                  are counted and bounded;
   4. indices    - the GPU's winning start is the oracle's unless their oracle finals tie
-                  within TAU or a near-tie was met.
+                  within TAU or the paths split at a near-tie.
 """
 import numpy as np
 
@@ -66,29 +68,78 @@ def check_exact_and_valid(pocket, G, ligs, srch, sel, score, start, steps, perio
     return float(np.max(err / np.maximum(1.0, np.abs(e64))))
 
 
-def check_optimal(pocket, G, ligs, srch, sel, score, start, orc, periodic=False):
-    """Checks 3 and 4 against a full oracle run `orc` (oracle.dock(..., per_start=True))."""
+def _split_is_near_tie(pocket, G, ligs, srch, lig, p, steps_gpu, periodic):
+    """The GPU's path from start p differs from the oracle's: replay the GPU's steps in FP64 and
+    check that every GPU decision is within TAU of the argmin, i.e. the two paths split at a
+    near-tie.  With several passes only total turns are reported; the pose must then rescore to
+    an FP64 value no better than the oracle allows (checked by the callers' rescoring)."""
+    if srch.passes > 1:
+        return True
+    rp = oracle.replay(pocket, G, ligs, srch, np.array([lig]), np.array([p]), steps_gpu[None], periodic=periodic)
+    B = ligs.n_rot[lig]
+    eg, em = rp["e_given"][0, :B], rp["e_min"][0, :B]
+    return bool(np.all(eg - em <= tol(em)))
+
+
+def check_optimal(pocket, G, ligs, srch, sel, score, start, orc, finals, start_steps, periodic=False,
+                  max_diverged=0.05):
+    """Checks 3 and 4 against a full oracle run `orc` (oracle.dock(..., per_start=True)), given the
+    GPU's per-start finals [n][N] and steps [n][N][16].
+
+    For every ligand:
+      * at the oracle's winning start p_or, if the GPU took the oracle's path (same steps; exact
+        ties broken to the lowest step on both sides count as the same path), its final there is
+        the oracle's best within TAU, so the GPU's best is no worse than the oracle's;
+      * at the GPU's winning start, if the oracle took the GPU's path, the GPU's best is the
+        oracle's final there within TAU, so it is no better than the oracle's best;
+      * if the two winning starts differ and both paths agree, the oracle's finals at the two
+        starts tie within TAU.
+    A ligand is excused from a bound only where the paths are shown to split at a near-tie: the
+    GPU's steps at that start, replayed in FP64, are each within TAU of the argmin (or, with start
+    selection, the start was not among the GPU's selected starts because of a near-tie in the rigid
+    ranking).  Such ligands are counted and may be at most `max_diverged` of the docked ligands
+    (at least one).  Returns that count."""
     sel = np.asarray(sel)
-    n_flag = 0
     ok = np.isfinite(orc["best"])
     assert np.array_equal(ok, np.isfinite(score))
     idx = np.flatnonzero(ok)
-    g_start = oracle.greedy_starts(pocket, G, ligs, srch, sel[idx], start[idx], periodic=periodic)
-    for n, i in enumerate(idx):
-        s_or, p_or = orc["best"][i], orc["start"][i]
-        gap_or = orc["start_gap"][i, p_or]
-        f_or_at_gpu, gap_at_gpu = g_start["final"][n], g_start["gap"][n]
-        clean = gap_or >= TAU and gap_at_gpu >= TAU
-        if gap_or >= TAU:
-            assert score[i] <= s_or + tol(s_or), f"ligand {sel[i]}: GPU {score[i]} worse than oracle {s_or}"
-        if gap_at_gpu >= TAU:
-            assert score[i] >= s_or - tol(s_or), f"ligand {sel[i]}: GPU {score[i]} better than oracle {s_or}"
-            assert abs(score[i] - f_or_at_gpu) <= tol(f_or_at_gpu)
-        if start[i] != p_or:
-            assert abs(f_or_at_gpu - s_or) <= tol(s_or) or not clean, \
-                f"ligand {sel[i]}: start {start[i]} vs oracle {p_or}"
-        n_flag += not clean
-    return n_flag
+    f_or, st_or = orc["finals"], orc["start_steps"]
+    n_div = 0
+    for i in idx:
+        lig = sel[i]
+        B = ligs.n_rot[lig]
+        s_or, p_or, p_g = orc["best"][i], int(orc["start"][i]), int(start[i])
+        diverged = False
+        # upper bound: the GPU at the oracle's winning start
+        if not np.isfinite(finals[i, p_or]):
+            assert srch.sweep_top, f"ligand {lig}: oracle's winning start {p_or} not searched"
+            diverged = True  # the GPU's FP32 rigid ranking put p_or just outside its top K
+        elif np.array_equal(start_steps[i, p_or, :B], st_or[i, p_or, :B]):
+            assert abs(finals[i, p_or] - s_or) <= tol(s_or), \
+                f"ligand {lig}: same path at start {p_or}, GPU final {finals[i, p_or]} vs oracle {s_or}"
+            assert score[i] <= s_or + tol(s_or), f"ligand {lig}: GPU {score[i]} worse than oracle {s_or}"
+        else:
+            assert _split_is_near_tie(pocket, G, ligs, srch, lig, p_or, start_steps[i, p_or], periodic), \
+                f"ligand {lig}: GPU path at start {p_or} leaves the oracle's at a decision that is not a near-tie"
+            diverged = True
+        # lower bound: the oracle at the GPU's winning start
+        same_at_gpu = np.isfinite(f_or[i, p_g]) and np.array_equal(start_steps[i, p_g, :B], st_or[i, p_g, :B])
+        if same_at_gpu:
+            assert abs(score[i] - f_or[i, p_g]) <= tol(f_or[i, p_g]), \
+                f"ligand {lig}: same path at start {p_g}, GPU {score[i]} vs oracle {f_or[i, p_g]}"
+            assert score[i] >= s_or - tol(s_or), f"ligand {lig}: GPU {score[i]} better than oracle {s_or}"
+        else:
+            # the GPU's own path was validated decision by decision (check 2); with selection the
+            # oracle may not have searched p_g at all (near-tie in the rigid ranking)
+            assert np.isfinite(f_or[i, p_g]) or srch.sweep_top, f"ligand {lig}: start {p_g} unsearched by the oracle"
+            diverged = True
+        # indices: with both paths shared, a different winning start is a tie between starts
+        if p_g != p_or and not diverged:
+            assert abs(f_or[i, p_g] - s_or) <= tol(s_or), f"ligand {lig}: start {p_g} vs oracle {p_or}"
+        n_div += diverged
+    assert n_div <= max(1, int(np.ceil(max_diverged * len(idx)))), \
+        f"{n_div} of {len(idx)} ligands diverge from the oracle at near-ties"
+    return n_div
 
 
 def check_per_start(pocket, G, ligs, srch, finals_gpu, steps_gpu, orc, periodic=False):

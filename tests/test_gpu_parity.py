@@ -239,8 +239,9 @@ def test_screen_pocket48_lib100_full(P, p48):
     assert np.array_equal(g["score"], g["finals"].min(1))
     assert np.array_equal(g["start"], np.argmin(g["finals"], 1))
     e = check_exact_and_valid(pocket, G, ligs, W.search, np.arange(ligs.n_lig), g["score"], g["start"], g["steps"])
-    n_flag = check_optimal(pocket, G, ligs, W.search, np.arange(ligs.n_lig), g["score"], g["start"], orc)
-    say(f"best: rescoring max rel err {e:.3g}, {n_flag} ligands with near-ties")
+    n_flag = check_optimal(pocket, G, ligs, W.search, np.arange(ligs.n_lig), g["score"], g["start"], orc,
+                           g["finals"], g["start_steps"])
+    say(f"best: rescoring max rel err {e:.3g}, {n_flag} ligands split from the oracle at near-ties")
     assert g["poses"] == oracle.pose_count(ligs.n_rot, orc["status"], W.search.n_starts, W.search.n_steps)
 
 
@@ -251,10 +252,11 @@ def test_screen_tiny_against_exhaustive(P):
     srch = I.make_search(8, 2, 8, 2.0, pocket.center)
     say("screen tiny ligands S=8 vs exhaustive")
     dp = P.DevicePocket(pocket)
-    g = _screen(P, dp, ligs, srch)
+    g = _screen(P, dp, ligs, srch, start_scores=True)
     orc = oracle.dock(pocket, G, ligs, srch, per_start=True)
     check_exact_and_valid(pocket, G, ligs, srch, np.arange(ligs.n_lig), g["score"], g["start"], g["steps"])
-    check_optimal(pocket, G, ligs, srch, np.arange(ligs.n_lig), g["score"], g["start"], orc)
+    check_optimal(pocket, G, ligs, srch, np.arange(ligs.n_lig), g["score"], g["start"], orc, g["finals"],
+                  g["start_steps"])
     nrot = ligs.n_rot
     for l in range(ligs.n_lig):
         ex, _, _ = oracle.exhaustive(pocket, G, ligs, srch, l)
@@ -272,14 +274,14 @@ def test_screen_edge_cases(P):
         srch = I.make_search(4, 2, S, 4.0, pocket.center)
         say(f"screen edge-case library ({ligs.n_lig} ligands, n up to 129, B up to 17) S={S}")
         dp = P.DevicePocket(pocket)
-        g = _screen(P, dp, ligs, srch)
+        g = _screen(P, dp, ligs, srch, start_scores=True)
         st = oracle.status(ligs)
         assert np.array_equal(g["status"], st)
         assert np.all(np.isinf(g["score"][st != 0])) and np.all(g["start"][st != 0] == -1)
         sel = np.arange(ligs.n_lig)
         check_exact_and_valid(pocket, G, ligs, srch, sel, g["score"], g["start"], g["steps"])
         orc = oracle.dock(pocket, G, ligs, srch, per_start=True)
-        check_optimal(pocket, G, ligs, srch, sel, g["score"], g["start"], orc)
+        check_optimal(pocket, G, ligs, srch, sel, g["score"], g["start"], orc, g["finals"], g["start_steps"])
         assert g["poses"] == oracle.pose_count(ligs.n_rot, st, srch.n_starts, S)
 
 
@@ -296,11 +298,11 @@ def test_32_atom_types(P):
         g = dp.view().cpu().numpy()
         err = np.abs(g.astype(np.float64) - G) / np.maximum(1.0, np.abs(G))
         assert err.max() <= 1e-6
-        r = _screen(P, dp, ligs, srch)
+        r = _screen(P, dp, ligs, srch, start_scores=True)
         sel = np.arange(ligs.n_lig)
         check_exact_and_valid(pocket, G, ligs, srch, sel, r["score"], r["start"], r["steps"])
         orc = oracle.dock(pocket, G, ligs, srch, per_start=True)
-        check_optimal(pocket, G, ligs, srch, sel, r["score"], r["start"], orc)
+        check_optimal(pocket, G, ligs, srch, sel, r["score"], r["start"], orc, r["finals"], r["start_steps"])
     assert t_used.max() >= 16  # the upper half of the table is exercised
 
 
@@ -411,30 +413,60 @@ def test_merge_pockets_vs_definition(P, n_pockets, n):
 # Full-size configuration 2 (96^3 x 16 grid, 256 x 32 starts, S = 256) on a stratified sample
 # ------------------------------------------------------------------------------------------------
 
+@pytest.mark.timeout(600)
 def test_pocket96_lib100k_sample_full_search(P):
     W = I.workload("pocket96-lib100k")
     pocket = W.pockets[0]
     lib_all = W.ligands(n_lig=20000)
     n, b = lib_all.n_atoms, lib_all.n_rot
     rng = np.random.default_rng(11)
-    pick = set(rng.choice(20000, 40, replace=False).tolist())
-    pick |= {int(np.argmax(n)), int(np.argmax(b)), int(np.argmin(n))}
-    pick |= set(np.flatnonzero(b == 12)[:3].tolist()) | set(np.flatnonzero(b == 0)[:2].tolist())
-    small = np.flatnonzero((b >= 2) & (n <= 17))[:2]
-    pick |= set(small.tolist())
+    # optimality sample, stratified: the largest and smallest ligands, the most and the fewest
+    # torsions, small flexible ligands and typical (median-sized) ones
+    med = np.flatnonzero((np.abs(n - np.median(n)) <= 2) & (np.abs(b - np.median(b)) <= 1))
+    strata = [np.flatnonzero(n == n.max())[:1], np.flatnonzero(n == n.min())[:1],
+              np.flatnonzero(b == 12)[:3], np.flatnonzero(b == 0)[:2],
+              np.flatnonzero((b >= 2) & (n <= 17))[:2], rng.choice(med, 8, replace=False)]
+    opt = np.unique(np.concatenate(strata))
+    assert len(opt) >= 16
+    pick = set(rng.choice(20000, 40, replace=False).tolist()) | set(opt.tolist())
     sel = np.array(sorted(pick))
     ligs = lib_all.subset(sel)
-    say(f"pocket96-lib100k sample of {len(sel)} ligands, 96^3 grid, full search, bench launch configuration")
+    say(f"pocket96-lib100k sample of {len(sel)} ligands ({len(opt)} for optimality: n {n[opt].min()}-{n[opt].max()}, "
+        f"B {b[opt].min()}-{b[opt].max()}), 96^3 grid, full search, bench launch configuration")
     dp = P.DevicePocket(pocket)
+    g = _screen(P, dp, ligs, W.search, start_scores=True, starts_per_item=256, waves_per_block=4)
     G = oracle.build_grids(pocket)  # the oracle's own grid
-    g = _screen(P, dp, ligs, W.search, starts_per_item=256, waves_per_block=4)
     e = check_exact_and_valid(pocket, G, ligs, W.search, np.arange(len(sel)), g["score"], g["start"], g["steps"])
     say(f"pocket96 sample: rescoring max rel err {e:.3g}")
-    # optimality on the small ligands with a full oracle run
-    loc = np.array([int(np.flatnonzero(sel == s)[0]) for s in small])
+    loc = np.searchsorted(sel, opt)
     orc = oracle.dock(pocket, G, ligs, W.search, sel=loc, per_start=True)
-    check_optimal(pocket, G, ligs, W.search, loc, g["score"][loc], g["start"][loc], orc)
+    n_div = check_optimal(pocket, G, ligs, W.search, loc, g["score"][loc], g["start"][loc], orc, g["finals"][loc],
+                          g["start_steps"][loc], max_diverged=0.1)
+    say(f"pocket96 optimality: {len(loc)} ligands, {n_div} split from the oracle at near-ties")
     assert g["poses"] == oracle.pose_count(ligs.n_rot, g["status"], W.search.n_starts, W.search.n_steps)
+
+
+@pytest.mark.timeout(600)
+def test_pockets4_heavy_tail_on_the_128_pocket(P):
+    """The 250k-ligand workload's largest pocket (128^3 x 16 types) with two of its heavy-tail
+    ligands (80-120 atoms), full 8192-start search, against the oracle on its own 128^3 grid."""
+    W = I.workload("pockets4-lib250k")
+    pocket = W.pockets[3]
+    assert pocket.dims == (128, 128, 128)
+    lib_all = W.ligands(n_lig=2000)
+    heavy = np.flatnonzero((lib_all.n_atoms >= 80) & (lib_all.n_rot >= 4))[:2]
+    ligs = lib_all.subset(heavy)
+    say(f"pockets4 128^3 pocket, heavy ligands {heavy.tolist()} (n {ligs.n_atoms.tolist()}, "
+        f"B {ligs.n_rot.tolist()}), full search")
+    dp = P.DevicePocket(pocket)
+    g = _screen(P, dp, ligs, W.search, start_scores=True)
+    G = oracle.build_grids(pocket)
+    sel = np.arange(ligs.n_lig)
+    e = check_exact_and_valid(pocket, G, ligs, W.search, sel, g["score"], g["start"], g["steps"])
+    orc = oracle.dock(pocket, G, ligs, W.search, per_start=True)
+    n_div = check_optimal(pocket, G, ligs, W.search, sel, g["score"], g["start"], orc, g["finals"], g["start_steps"])
+    say(f"128^3 heavy: rescoring max rel err {e:.3g}, best {g['score'].tolist()} vs oracle {orc['best'].tolist()}, "
+        f"{n_div} split at near-ties")
 
 
 @pytest.mark.parametrize("S", [300, 1024])
@@ -453,7 +485,7 @@ def test_screen_many_steps(P, S):
     assert st["agree"] >= 0.95 * st["starts"]
     sel = np.arange(ligs.n_lig)
     check_exact_and_valid(pocket, G, ligs, srch, sel, g["score"], g["start"], g["steps"])
-    check_optimal(pocket, G, ligs, srch, sel, g["score"], g["start"], orc)
+    check_optimal(pocket, G, ligs, srch, sel, g["score"], g["start"], orc, g["finals"], g["start_steps"])
     assert np.all(g["steps"] < S)
 
 

@@ -70,8 +70,8 @@ def test_search_budget_matches_oracle(env, top, passes):
     f = orc["finals"]
     orc["best"] = f.min(1)
     orc["start"] = np.argmin(f, 1).astype(np.int32)
-    n_flag = check_optimal(pocket, G, ligs, srch, sel, g["score"], g["start"], orc)
-    say(f"{n_flag} ligands with near-ties")
+    n_flag = check_optimal(pocket, G, ligs, srch, sel, g["score"], g["start"], orc, g["finals"], g["start_steps"])
+    say(f"{n_flag} ligands whose paths split from the oracle's at near-ties")
     B = ligs.n_rot
     assert g["poses"] == int(np.sum(QT + n_searched * passes * B * (srch.n_steps - 1)))
 
@@ -102,8 +102,8 @@ def test_restarts_match_oracle(env, restarts, passes):
     assert np.array_equal(g["score"], g["finals"].min(1)) and np.array_equal(g["start"], np.argmin(g["finals"], 1))
     sel = np.arange(ligs.n_lig)
     check_exact_and_valid(pocket, G, ligs, srch, sel, g["score"], g["start"], g["steps"])
-    n_flag = check_optimal(pocket, G, ligs, srch, sel, g["score"], g["start"], orc)
-    say(f"{n_flag} ligands with near-ties; restart winners: {int(np.sum(g['start'] >= QT))} of {ligs.n_lig}")
+    n_flag = check_optimal(pocket, G, ligs, srch, sel, g["score"], g["start"], orc, g["finals"], g["start_steps"])
+    say(f"{n_flag} ligands split at near-ties; restart winners: {int(np.sum(g['start'] >= QT))} of {ligs.n_lig}")
     B = ligs.n_rot
     assert g["poses"] == int(np.sum(N * (1 + passes * B * (srch.n_steps - 1))))
 
