@@ -115,7 +115,7 @@ def test_refused_rescore_enqueues_nothing(env):
                 torch.full((n, 4), -7.0, device=dev), torch.full((n, 4), -7.0, device=dev),
                 torch.full((n,), -7.0, device=dev), torch.full((n,), -7, dtype=torch.int32, device=dev)]
     before = [t.clone() for t in sentinel]
-    pk = pocket.pocket
+    pk = pocket
     eps = np.array(pk.type_eps, dtype=np.float64).copy()
     eps[-1] = -0.1
     with pytest.raises(dock.DockError):
