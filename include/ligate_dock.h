@@ -203,6 +203,27 @@ int dock_screen(const dock_grid_desc *g, const float *d_grids, const void *d_pac
                 void *d_ws, size_t *ws_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid allocation): dock_screen with the
+ * same arguments and outputs, minus the workspace.  Its scratch is a fixed
+ * device array of DOCK_NOALLOC_SCRATCH_BYTES inside the library, one per GPU,
+ * allocated when the library's code object is loaded and held until the
+ * process ends; the call allocates nothing.  The scratch needed is that of
+ * dock_screen's workspace query (about 25 bytes per ligand, plus 4 * sweep_top
+ * per ligand with start selection); a screen needing more returns
+ * DOCK_ERR_LIMIT before anything is enqueued.  Every call on one GPU shares that
+ * GPU's array and clears what it needs on the device: calls that overlap on one
+ * GPU (two streams, or two host threads) race and give undefined results; calls
+ * in sequence on one stream are safe.  The first call on each device looks up
+ * that device's array (a HIP symbol query, no allocation).
+ */
+#define DOCK_NOALLOC_SCRATCH_BYTES (32u << 20)
+int dock_screen_noalloc(const dock_grid_desc *g, const float *d_grids, const void *d_pack, int32_t n_lig,
+                        int64_t n_atoms_total, const dock_search *s, float *d_best_score, int32_t *d_best_start,
+                        uint16_t *d_best_steps, float *d_start_scores, uint16_t *d_start_steps,
+                        uint64_t *d_pose_count, void *stream);
+
+/*
  * Paper §2: the poses the docking generates are filtered, and the survivors are
  * rescored with a function that adds physico-chemical information.
  * Pose filtering and rescoring after dock_screen.  For every packed ligand: the

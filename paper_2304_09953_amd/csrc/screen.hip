@@ -28,6 +28,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 
@@ -1531,6 +1532,38 @@ static int screen_enqueue(const dock_grid_desc *gd, const float *d_grids, const 
     return dispatch_boundary<DOCK_LAYOUT_LINEAR>(gd->boundary, A.s.S, A, d_best_score, d_best_start, d_best_steps, st);
 }
 
+// Scratch of dock_screen_noalloc: one copy per GPU, allocated with the code object and held
+// until the process ends.  Host code never uses this name as an address: the device address of
+// each GPU's copy comes from hipGetSymbolAddress (noalloc_scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[DOCK_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch, looked up once per device with that device current.
+static int noalloc_scratch_ptr(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_last_error("dock_screen_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+        return DOCK_ERR_HIP;
+    }
+    LIGATE_REQUIRE(dev >= 0 && dev < kMaxDevices, DOCK_ERR_LIMIT, "device %d beyond %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            set_last_error("dock_screen_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+            return DOCK_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DOCK_OK;
+}
+
 }  // namespace ligate
 
 extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const void *d_pack, int32_t n_lig,
@@ -1550,6 +1583,26 @@ extern "C" int dock_screen(const dock_grid_desc *gd, const float *d_grids, const
     LIGATE_REQUIRE(*ws_bytes >= need, DOCK_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", *ws_bytes, need);
     return screen_enqueue(gd, d_grids, d_pack, n_lig, n_atoms_total, sd, d_best_score, d_best_start, d_best_steps,
                           d_start_scores, d_start_steps, d_pose_count, d_ws, (hipStream_t)stream);
+}
+
+extern "C" int dock_screen_noalloc(const dock_grid_desc *gd, const float *d_grids, const void *d_pack, int32_t n_lig,
+                                   int64_t n_atoms_total, const dock_search *sd, float *d_best_score,
+                                   int32_t *d_best_start, uint16_t *d_best_steps, float *d_start_scores,
+                                   uint16_t *d_start_steps, uint64_t *d_pose_count, void *stream) {
+    LIGATE_ABI_RANGE();
+    size_t need = 0;
+    int rc = screen_ws_need(gd, sd, n_lig, n_atoms_total, &need);
+    if (rc) return rc;
+    LIGATE_REQUIRE(need <= (size_t)DOCK_NOALLOC_SCRATCH_BYTES, DOCK_ERR_LIMIT,
+                   "this screen needs %zu bytes of scratch, the allocation-free entry point has %zu", need,
+                   (size_t)DOCK_NOALLOC_SCRATCH_BYTES);
+    LIGATE_REQUIRE(d_grids && d_pack && d_best_score && d_best_start && d_best_steps, DOCK_ERR_INVALID_ARG,
+                   "NULL array");
+    void *ptr = nullptr;
+    rc = noalloc_scratch_ptr(&ptr);
+    if (rc) return rc;
+    return screen_enqueue(gd, d_grids, d_pack, n_lig, n_atoms_total, sd, d_best_score, d_best_start, d_best_steps,
+                          d_start_scores, d_start_steps, d_pose_count, ptr, (hipStream_t)stream);
 }
 
 extern "C" int dock_score_poses(const dock_grid_desc *gd, const float *d_grids, const void *d_pack, int32_t n_lig,

@@ -27,7 +27,7 @@ BOUNDARY_PERIODIC = 1
 LIG_STATUS = {0: "ok", 1: "n_atoms", 2: "type", 3: "n_bonds", 4: "bond_index", 5: "degree", 6: "not_tree",
               7: "terminal_rotatable", 8: "n_torsions"}
 
-EXPORTS = ("dock_grid_bytes", "dock_build_grids", "dock_pack_ligands", "dock_screen", "dock_topk",
+EXPORTS = ("dock_grid_bytes", "dock_build_grids", "dock_pack_ligands", "dock_screen", "dock_screen_noalloc", "dock_topk",
            "dock_merge_pockets", "dock_score_poses", "dock_rescore", "dock_error_string", "dock_last_error")
 
 
@@ -72,6 +72,8 @@ def load() -> ctypes.CDLL:
         lib.dock_build_grids.argtypes = [P(GridDesc), vp, vp, i32, P(TypeParam), P(Potential), vp, vp]
         lib.dock_pack_ligands.argtypes = [vp, vp, vp, vp, vp, vp, i32, i64, i32, vp, P(sz), vp, vp]
         lib.dock_screen.argtypes = [P(GridDesc), vp, vp, i32, i64, P(SearchDesc), vp, vp, vp, vp, vp, vp, vp, P(sz), vp]
+        lib.dock_screen_noalloc.argtypes = [P(GridDesc), vp, vp, i32, i64, P(SearchDesc), vp, vp, vp, vp, vp, vp,
+                                            vp]
         lib.dock_topk.argtypes = [vp, vp, i64, i32, vp, vp, vp, P(sz), vp]
         lib.dock_score_poses.argtypes = [P(GridDesc), vp, vp, i32, i64, P(SearchDesc), vp, vp, vp, i64, vp, vp]
         lib.dock_merge_pockets.argtypes = [vp, i32, i64, vp, vp, vp]
@@ -190,6 +192,15 @@ def screen(desc: GridDesc, grids, pack, n_lig: int, n_atoms: int, search: Search
                               _ptr(best_score), _ptr(best_start), _ptr(best_steps), _ptr(start_scores),
                               _ptr(start_steps), _ptr(pose_count), _ptr(ws), ctypes.byref(size), _stream(stream)),
            "dock_screen")
+
+
+def screen_noalloc(desc: GridDesc, grids, pack, n_lig: int, n_atoms: int, search: SearchDesc, best_score, best_start,
+                   best_steps, start_scores=None, pose_count=None, stream=None, start_steps=None):
+    """dock_screen_noalloc: the screen with the library's fixed device scratch (no workspace)."""
+    _check(load().dock_screen_noalloc(ctypes.byref(desc), _ptr(grids), _ptr(pack), n_lig, n_atoms,
+                                      ctypes.byref(search), _ptr(best_score), _ptr(best_start), _ptr(best_steps),
+                                      _ptr(start_scores), _ptr(start_steps), _ptr(pose_count), _stream(stream)),
+           "dock_screen_noalloc")
 
 
 def topk_ws_bytes(n: int, k: int) -> int:

@@ -160,6 +160,20 @@ def test_size_queries_and_argument_errors():
         assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, 10, 300, ctypes.byref(sr), None, None, None,
                                None, None, None, None, ctypes.byref(sz), None) == code, (R, init, top)
     assert "DOCK_MAX_RESTARTS 64" in open(os.path.join(ROOT, "include", "ligate_dock.h")).read()
+    # the allocation-free screen refuses, before any HIP call, a screen whose scratch exceeds its array
+    assert "#define DOCK_NOALLOC_SCRATCH_BYTES (32u << 20)" in open(os.path.join(ROOT, "include", "ligate_dock.h")).read()
+    big = 2_000_000  # about 25 bytes of scratch per ligand: 50 MB > 32 MiB
+    assert lib.dock_screen(ctypes.byref(_desc(dock)), None, None, big, 300, ctypes.byref(s), None, None, None, None,
+                           None, None, None, ctypes.byref(sz), None) == 0
+    assert sz.value > (32 << 20)
+    assert lib.dock_screen_noalloc(ctypes.byref(_desc(dock)), fake, fake, big, 300, ctypes.byref(s), fake, fake, fake,
+                                   None, None, None, None) == -2
+    assert b"scratch" in lib.dock_last_error()
+    sel_big = dock.SearchDesc(4, fake, 2, fake, 64, 2.5, 10.0, 0, 0, 3, 1)
+    assert lib.dock_screen_noalloc(ctypes.byref(_desc(dock)), fake, fake, 10, 300, ctypes.byref(s_bad), fake, fake,
+                                   fake, None, None, None, None) == -2  # the screen's own limits come first
+    assert lib.dock_screen_noalloc(ctypes.byref(_desc(dock)), None, fake, 10, 300, ctypes.byref(sel_big), fake, fake,
+                                   fake, None, None, None, None) == -1
     # dock_rescore checks every argument, the type table included, before its first launch
     T = 4
     params = (dock.TypeParam * T)(*[dock.TypeParam(1.5, 0.1 if t < T - 1 else -0.1, 0.0) for t in range(T)])
