@@ -21,8 +21,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ligands docked/sec and poses scored/sec on 1 MI355X; recall@top1% with surrogate"
 PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 64 FMA lanes/clk x 2 FLOP x 2.4 GHz
-FLOP_RIGID_ATOM = 46           # rotation 18 + grid coordinates 6 + trilinear 21 + sum 1
-FLOP_SWEEP_LOOKUP = 40         # circle position 12 + grid coordinates 6 + trilinear 21 + sum 1
+# Algorithmic FLOP per lookup, in the units of the scope table: a rigid-start atom 48 (transform 18,
+# interpolation about 30), a sweep lookup 36 (circle-form move 6, interpolation about 30).  The kernel's
+# own instruction-level count (an FMA as 2) is 46 and 40; it is reported beside them.
+FLOP_RIGID_ATOM = 48
+FLOP_SWEEP_LOOKUP = 36
+FLOP_RIGID_ATOM_KERNEL = 46    # rotation 18 + grid coordinates 6 + trilinear 21 + sum 1
+FLOP_SWEEP_LOOKUP_KERNEL = 40  # circle position 12 + grid coordinates 6 + trilinear 21 + sum 1
 BYTES_PER_LOOKUP = 32          # eight FP32 corners
 COUNTERS = os.path.join(ROOT, "profiles", "screen_counters.json")
 SCREEN_SRC = os.path.join(ROOT, "paper_2304_09953_amd", "csrc", "screen.hip")
@@ -116,9 +121,39 @@ def summarize_counters(out_dir):
     print(json.dumps(out, indent=1))
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_sample(ligs, seed: int = 20240409):
+    """Seeded, stratified order of library ligands for the CPU baseline: the largest ligand, one with
+    the most torsions (12), one with none, the smallest, then seeded random draws."""
+    import numpy as np
+    n, b = ligs.n_atoms, ligs.n_rot
+    first = [int(np.argmax(n)), int(np.flatnonzero(b == b.max())[0]), int(np.flatnonzero(b == 0)[0]),
+             int(np.argmin(n))]
+    rng = np.random.default_rng(seed)
+    rest = [int(i) for i in rng.permutation(ligs.n_lig)[:256] if int(i) not in first]
+    out = []
+    for i in first + rest:
+        if i not in out:
+            out.append(i)
+    return out
+
+
 def cpu_baseline(W, ligs, budget_s):
-    """The FP64 oracle on the host: the first ligands of the library for about budget_s seconds on all
-    threads OpenMP uses, then the first ligand alone on one thread."""
+    """The FP64 oracle on the host, on all threads OpenMP uses: a seeded stratified sample of the
+    library (cpu_sample) docked one ligand at a time with the full search until budget_s seconds have
+    passed (the four strata always run), then one ligand of median atom and torsion counts on one thread.  Rates are the
+    sample's own; the library estimate rescales the sample's lookup rate by the library's mean
+    lookups per ligand.  Grid build excluded."""
     import numpy as np
 
     import oracle
@@ -126,26 +161,54 @@ def cpu_baseline(W, ligs, budget_s):
     log("cpu baseline: oracle grids")
     G = oracle.build_grids(pocket)
     cores = oracle.get_threads()
-    done, poses, t0 = 0, 0, time.perf_counter()
+    Q, S = W.search.n_starts, W.search.n_steps
     n_rot = ligs.n_rot
-    pose_count = lambda i: W.search.n_starts * (1 + int(n_rot[i]) * (W.search.n_steps - 1))  # noqa: E731
-    while time.perf_counter() - t0 < budget_s and done < ligs.n_lig:
-        oracle.dock(pocket, G, ligs, W.search, sel=np.array([done]))
-        poses += pose_count(done)
-        done += 1
-        log(f"cpu baseline: {done} ligands, {time.perf_counter() - t0:.1f} s")
+
+    def lookups(idx):
+        """Q T (n + (S - 1) sum_k |M_k|) per ligand, moving sets from the oracle's own topology."""
+        out = []
+        for i in np.asarray(idx).tolist():
+            tp = oracle.topology(ligs, i)
+            out.append(Q * (ligs.n_atoms[i] + (S - 1) * float(tp["moving"].sum())) if tp["status"] == 0 else 0.0)
+        return np.array(out)
+
+    pose_count = lambda i: Q * (1 + int(n_rot[i]) * (S - 1))  # noqa: E731
+    order = cpu_sample(ligs)
+    done, poses, t0 = [], 0, time.perf_counter()
+    for i in order:
+        if len(done) >= 4 and time.perf_counter() - t0 >= budget_s:
+            break
+        oracle.dock(pocket, G, ligs, W.search, sel=np.array([i]))
+        poses += pose_count(i)
+        done.append(i)
+        log(f"cpu baseline: {len(done)} ligands (last: n {ligs.n_atoms[i]}, B {n_rot[i]}), "
+            f"{time.perf_counter() - t0:.1f} s")
     dt = time.perf_counter() - t0
+    lib_lookups = float(lookups(np.random.default_rng(7).choice(ligs.n_lig, min(4000, ligs.n_lig),
+                                                                 replace=False)).mean())
+    samp_rate = float(lookups(done).sum()) / dt
+    # a typical ligand: the first with the median atom count and the median torsion count
+    med = int(np.flatnonzero((ligs.n_atoms == int(np.median(ligs.n_atoms))) & (n_rot == int(np.median(n_rot))))[0])
     oracle.set_threads(1)
     t1 = time.perf_counter()
-    oracle.dock(pocket, G, ligs, W.search, sel=np.array([0]))
+    oracle.dock(pocket, G, ligs, W.search, sel=np.array([med]))
     dt1 = time.perf_counter() - t1
     oracle.set_threads(cores)
-    log(f"cpu baseline: ligand 0 on one thread, {dt1:.1f} s")
-    return {"value": done / dt, "unit": "ligands/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {done} ligands of the library, full search, FP64 oracle, grid build excluded",
+    log(f"cpu baseline: median ligand {med} on one thread, {dt1:.1f} s")
+    return {"value": len(done) / dt, "unit": "ligands/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": (f"sample rate: {len(done)} ligands of a seeded stratified sample of the library (the "
+                       "largest, one with 12 torsions, one with none, the smallest, then random draws), full "
+                       "search, FP64 oracle, grid build excluded"),
+            "sample_ids": done, "sample_n_atoms": [int(ligs.n_atoms[i]) for i in done],
+            "sample_n_rot": [int(n_rot[i]) for i in done],
             "poses_per_sec": poses / dt, "seconds": round(dt, 2),
-            "one_core": {"value": 1 / dt1, "unit": "ligands/s", "poses_per_sec": pose_count(0) / dt1,
-                         "sample": "ligand 0 of the library, full search, one OpenMP thread",
+            "library_estimate_ligands_per_s": samp_rate / lib_lookups,
+            "library_estimate_note": ("the sample's lookups per second over the mean lookups per ligand of 4000 "
+                                      "seeded library ligands"),
+            "one_core": {"value": 1 / dt1, "unit": "ligands/s", "poses_per_sec": pose_count(med) / dt1,
+                         "sample": f"ligand {med} (median atom and torsion counts, n {int(ligs.n_atoms[med])}, "
+                                   f"B {int(n_rot[med])}), full search, one OpenMP thread",
                          "seconds": round(dt1, 2)}}
 
 
@@ -578,7 +641,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-lig", type=int, default=None, help="dock only the first N ligands (a subset workload)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
                     help="write the screen's counter summary from rocprofv3 --pmc CSV directories in DIR")
@@ -717,6 +780,7 @@ def main():
     assert poses == int(scr.pose_count.cpu().item())
     lookups = int(np.sum(QT * (n_at + (S - 1) * sum_m)))
     flop = int(np.sum(QT * (FLOP_RIGID_ATOM * n_at + FLOP_SWEEP_LOOKUP * (S - 1) * sum_m)))
+    flop_kernel = int(np.sum(QT * (FLOP_RIGID_ATOM_KERNEL * n_at + FLOP_SWEEP_LOOKUP_KERNEL * (S - 1) * sum_m)))
     achieved = flop / (screen_ms * 1e-3)
     best = scr.best_score.cpu().numpy()
     assert np.all(np.isfinite(best[ok]))
@@ -767,6 +831,11 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_NONPACKED, "traffic": traffic_from_counters(),
                      "kernel": "k_screen (+ its planning and replay kernels, inside the same events)",
                      "algorithmic_flop_per_launch": flop, "lookups_per_launch": lookups,
+                     "flop_units": {"rigid_atom": FLOP_RIGID_ATOM, "sweep_lookup": FLOP_SWEEP_LOOKUP},
+                     "kernel_count_units": {"rigid_atom": FLOP_RIGID_ATOM_KERNEL,
+                                            "sweep_lookup": FLOP_SWEEP_LOOKUP_KERNEL,
+                                            "achieved": flop_kernel / (screen_ms * 1e-3) / 1e12,
+                                            "frac": flop_kernel / (screen_ms * 1e-3) / PEAK_FP32_NONPACKED},
                      "gather_bytes_per_s": BYTES_PER_LOOKUP * lookups / (screen_ms * 1e-3)},
         "gather_roofline": gather,
         # the paper's only throughput figure, as context (not comparable: its ligands, sites, search
