@@ -246,3 +246,178 @@ def screen_buckets(pocket_dev, search, ligs, k: int = 1000, chunk: int = 16384, 
             log(f"bucket {bucket}: {len(idx)} ligands, starts/item {p}, waves/block {w}, "
                 f"{time.perf_counter() - t0:.2f} s")
     return top_s, top_i, best
+
+
+# ------------------------------------------------------------------------------------------------
+# Several binding sites from one pack (a ligand is ranked by its best site)
+# ------------------------------------------------------------------------------------------------
+
+class SitesChunkPipeline:
+    """Fixed device buffers for one chunk shape and several pockets, and a hipGraph of: pack the chunk
+    once; screen it against every pocket (each with its own tuned launch parameters); merge each
+    pocket's chunk scores into that pocket's running top-k; take each ligand's best pocket with
+    dock_merge_pockets and merge those into a running top-k of the best-site ranking."""
+
+    def __init__(self, pockets_dev, searches, shape: ChunkShape, n_types: int, k: int, params=None,
+                 use_graph: bool = True):
+        dev = pockets_dev[0].grids.device
+        n_p = len(pockets_dev)
+        assert len(searches) == n_p and n_p >= 1
+        params = params or [(0, 0)] * n_p
+        self.pockets, self.shape, self.k, self.n_types, self.n_p = pockets_dev, shape, k, n_types, n_p
+        L, A = shape.n_lig, shape.n_atoms
+        self.atom_off = torch.zeros(L + 1, dtype=torch.int32, device=dev)
+        self.bond_off = torch.zeros(L + 1, dtype=torch.int32, device=dev)
+        self.xyz = torch.zeros(3 * A, dtype=torch.float32, device=dev)
+        self.types = torch.zeros(A, dtype=torch.uint8, device=dev)
+        self.bonds = torch.zeros(2 * max(A, 1), dtype=torch.int32, device=dev)
+        self.rot = torch.zeros(max(A, 1), dtype=torch.uint8, device=dev)
+        self.pack = torch.empty(dock.pack_bytes(L, A, n_types), dtype=torch.uint8, device=dev)
+        self.status = torch.empty(L, dtype=torch.int32, device=dev)
+        self.searches = [P.DeviceSearch(s, starts_per_item=p, waves_per_block=w) for s, (p, w) in zip(searches, params)]
+        ws = max(dock.screen_ws_bytes(d.desc, L, A, s.desc) for d, s in zip(pockets_dev, self.searches))
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=dev)  # the screens run in turn on one stream
+        # per pocket: [running top-k | this chunk's best scores], global ligand ids beside them
+        self.scores = torch.full((n_p, k + L), float("inf"), dtype=torch.float32, device=dev)
+        self.ids = torch.full((n_p, k + L), 2 ** 31 - 1, dtype=torch.int32, device=dev)
+        self.best_start = torch.empty((n_p, L), dtype=torch.int32, device=dev)
+        self.best_steps = torch.empty((n_p, L * dock.MAX_TORSIONS), dtype=torch.int16, device=dev)
+        self.top_s = torch.empty((n_p, k), dtype=torch.float32, device=dev)
+        self.top_i = torch.empty((n_p, k), dtype=torch.int32, device=dev)
+        self.topk_ws = torch.empty(dock.topk_ws_bytes(k + L, k), dtype=torch.uint8, device=dev)
+        # best site: dock_merge_pockets over the rows [running k | chunk] (only the chunk part is used),
+        # then [running top-k | chunk's best-site scores] and its top-k
+        self.merged = torch.empty(k + L, dtype=torch.float32, device=dev)
+        self.site = torch.empty(k + L, dtype=torch.int32, device=dev)
+        self.site_scores = torch.full((k + L,), float("inf"), dtype=torch.float32, device=dev)
+        self.site_ids = torch.full((k + L,), 2 ** 31 - 1, dtype=torch.int32, device=dev)
+        self.site_top_s = torch.empty(k, dtype=torch.float32, device=dev)
+        self.site_top_i = torch.empty(k, dtype=torch.int32, device=dev)
+        self.graph = None
+        if use_graph:
+            self._capture()
+
+    def _enqueue(self):
+        L, A, k = self.shape.n_lig, self.shape.n_atoms, self.k
+        dock.pack_ligands(self.atom_off, self.xyz, self.types, self.bond_off, self.bonds, self.rot, self.n_types,
+                          self.pack, self.status)
+        for p, (dp, ds) in enumerate(zip(self.pockets, self.searches)):
+            dock.screen(dp.desc, dp.grids, self.pack, L, A, ds.desc, self.scores[p, k:], self.best_start[p],
+                        self.best_steps[p], self.ws)
+        for p in range(self.n_p):
+            dock.topk(self.scores[p], k, self.top_s[p], self.top_i[p], self.topk_ws, self.ids[p])
+            self.scores[p, :k].copy_(self.top_s[p])
+            self.ids[p, :k].copy_(self.top_i[p])
+        dock.merge_pockets(self.scores, self.merged, self.site)
+        self.site_scores[k:].copy_(self.merged[k:])
+        dock.topk(self.site_scores, k, self.site_top_s, self.site_top_i, self.topk_ws, self.site_ids)
+        self.site_scores[:k].copy_(self.site_top_s)
+        self.site_ids[:k].copy_(self.site_top_i)
+
+    def _capture(self):
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):  # warm-up outside the graph (first-launch host work)
+            self._enqueue()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.reset()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._enqueue()
+        torch.cuda.synchronize()
+
+    def reset(self):
+        self.scores.fill_(float("inf"))
+        self.ids.fill_(2 ** 31 - 1)
+        self.site_scores.fill_(float("inf"))
+        self.site_ids.fill_(2 ** 31 - 1)
+
+    def seed(self, tops, site_top):
+        """Running top-k of every pocket and of the best-site ranking (host arrays) into the buffers."""
+        k = self.k
+        for p, (s, i) in enumerate(tops):
+            self.scores[p, :k].copy_(torch.from_numpy(s))
+            self.ids[p, :k].copy_(torch.from_numpy(i))
+        self.site_scores[:k].copy_(torch.from_numpy(site_top[0]))
+        self.site_ids[:k].copy_(torch.from_numpy(site_top[1]))
+
+    def load(self, ligs, ids: np.ndarray):
+        """Copies a chunk (at most the capacity) into the fixed buffers; unused ligand slots become
+        empty ligands (status n_atoms, score +inf)."""
+        L, A = self.shape.n_lig, self.shape.n_atoms
+        n, a = ligs.n_lig, int(ligs.atom_off[-1])
+        assert n <= L and a <= A, (n, a, L, A)
+        off = np.full(L + 1, a, dtype=np.int32)
+        off[:n + 1] = ligs.atom_off
+        boff = np.full(L + 1, int(ligs.bond_off[-1]), dtype=np.int32)
+        boff[:n + 1] = ligs.bond_off
+        self.atom_off.copy_(torch.from_numpy(off))
+        self.bond_off.copy_(torch.from_numpy(boff))
+        self.xyz[:3 * a].copy_(torch.from_numpy(ligs.xyz.reshape(-1)))
+        self.types[:a].copy_(torch.from_numpy(ligs.types))
+        e = int(ligs.bond_off[-1])
+        if e:
+            self.bonds[:2 * e].copy_(torch.from_numpy(ligs.bonds.reshape(-1)))
+            self.rot[:e].copy_(torch.from_numpy(ligs.rot))
+        gid = np.full(L, 2 ** 31 - 1, dtype=np.int32)
+        gid[:n] = ids
+        g = torch.from_numpy(gid)
+        self.ids[:, self.k:].copy_(g.unsqueeze(0).expand(self.n_p, L))
+        self.site_ids[self.k:].copy_(g)
+
+    def run(self):
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self._enqueue()
+
+
+@dataclass
+class SitesResult:
+    top_s: np.ndarray       # [n_pockets, k] each pocket's top-k scores (ascending)
+    top_i: np.ndarray       # [n_pockets, k] their global ligand ids
+    best: np.ndarray        # [n_pockets, n_lig] every ligand's best score against every pocket
+    site_top_s: np.ndarray  # [k] best-site ranking: scores
+    site_top_i: np.ndarray  # [k] best-site ranking: global ids
+    site: np.ndarray        # [n_lig] each ligand's best pocket (-1 if docked nowhere)
+
+
+def screen_sites(pockets_dev, searches, ligs, k: int = 1000, chunk: int = 16384, tuned: bool = True,
+                 use_graph: bool = True, log=None, table_path: str | None = None) -> SitesResult:
+    """Screens a library against several pockets from one pack per chunk, bucket by bucket in
+    graph-replayed chunks, keeping each pocket's running top-k and the running top-k of the
+    best-site ranking."""
+    arch = arch_name()
+    n_p = len(pockets_dev)
+    buckets = size_bucket(ligs.n_atoms)
+    best = np.full((n_p, ligs.n_lig), np.inf, dtype=np.float32)
+    site = np.full(ligs.n_lig, -1, dtype=np.int32)
+    tops = [(np.full(k, np.inf, np.float32), np.full(k, 2 ** 31 - 1, np.int32)) for _ in range(n_p)]
+    site_top = (np.full(k, np.inf, np.float32), np.full(k, 2 ** 31 - 1, np.int32))
+    for bucket in range(len(BUCKET_EDGES) + 1):
+        idx = np.flatnonzero(buckets == bucket)
+        if len(idx) == 0:
+            continue
+        params = [lookup(arch, dp.pocket.dims, s.n_steps, bucket, table_path) if tuned else (0, 0)
+                  for dp, s in zip(pockets_dev, searches)]
+        pipe = SitesChunkPipeline(pockets_dev, searches, chunk_shape_for(ligs, idx, chunk), ligs.n_types, k, params,
+                                  use_graph)
+        pipe.reset()
+        pipe.seed(tops, site_top)
+        t0 = time.perf_counter()
+        for s in range(0, len(idx), chunk):
+            sel = idx[s:s + chunk]
+            pipe.load(ligs.subset(sel), ligs.ids[sel].astype(np.int32))
+            pipe.run()
+            best[:, sel] = pipe.scores[:, k:k + len(sel)].cpu().numpy()
+            site[sel] = pipe.site[k:k + len(sel)].cpu().numpy()
+        torch.cuda.synchronize()
+        tops = [(pipe.scores[p, :k].cpu().numpy(), pipe.ids[p, :k].cpu().numpy()) for p in range(n_p)]
+        site_top = (pipe.site_scores[:k].cpu().numpy(), pipe.site_ids[:k].cpu().numpy())
+        if log:
+            log(f"bucket {bucket}: {len(idx)} ligands x {n_p} pockets, launch parameters {params}, "
+                f"{time.perf_counter() - t0:.2f} s")
+    return SitesResult(np.stack([t[0] for t in tops]), np.stack([t[1] for t in tops]), best, site_top[0],
+                       site_top[1], site)
