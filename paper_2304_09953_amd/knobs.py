@@ -1,15 +1,17 @@
 """Bayesian tuning of the search's quality knobs.
 
 The paper tunes the docking engine's quality/performance knobs with a Bayesian optimiser (§3.3,
-LiGen autotuning: a method aimed at the cheapest configuration of a recurring, constrained job).
-Here the knobs are the number of quaternions Q, of translations T, of torsion steps S, of greedy
-passes, of swept starts (sweep_top) and of torsion restarts per rigid start (which the search runs
-only over every start, so they exclude sweep_top); the constraint is the recall of a reference ranking's top
-1 % on a sample library, the cost the screen's time per ligand.  The model is a Gaussian process
-per objective (log time, recall) over the knobs scaled to [0, 1] on a log2 axis; the next
+LiGen autotuning: 11 knobs and more than 6e7 configurations, explored by a method aimed at the
+cheapest configuration of a recurring, constrained job).  Here the knobs are the number of
+quaternions Q, of translations T and their radius, of torsion steps S, of greedy passes, of swept
+starts (sweep_top) and of torsion restarts per rigid start (which the search runs only over every
+start, so they exclude sweep_top): about 4.5e4 configurations, too many to screen them all.  The
+constraint is the recall of a reference ranking's top fraction on a sample library, the cost the
+screen's time per ligand.  The model is a Gaussian process per objective (log time, recall) over
+the knobs scaled to [0, 1] (log2 axes for the counts, a linear axis for the radius); the next
 configuration maximises expected improvement of the time weighted by the probability that the
 recall constraint holds.  Candidates are the discrete grid of knob values; every evaluation is a
-real screen (the caller's `evaluate`).  Host-side logic only: it orders screens.
+real screen (ScreenObjective, or the caller's `evaluate`).  Host-side logic only: it orders screens.
 """
 from __future__ import annotations
 
@@ -18,8 +20,13 @@ import math
 
 import numpy as np
 
-SPACE = {"n_quat": (32, 64, 128, 256), "n_trans": (8, 16, 32), "n_steps": (64, 128, 256), "passes": (1, 2),
-         "sweep_top": (0, 64, 256, 1024), "restarts": (0, 1, 2)}
+SPACE = {"n_quat": (16, 24, 32, 48, 64, 96, 128, 192, 256), "n_trans": (4, 8, 12, 16, 24, 32),
+         "radius": (2.0, 3.0, 4.0, 5.0), "n_steps": (32, 48, 64, 96, 128, 192, 256), "passes": (1, 2, 3),
+         "sweep_top": (0, 16, 32, 64, 128, 256, 512, 1024, 2048), "restarts": (0, 1, 2)}
+# the earlier, small space (390 configurations), kept for comparisons where enumeration is affordable
+SMALL_SPACE = {"n_quat": (32, 64, 128, 256), "n_trans": (8, 16, 32), "n_steps": (64, 128, 256), "passes": (1, 2),
+               "sweep_top": (0, 64, 256, 1024), "restarts": (0, 1, 2)}
+LINEAR_KNOBS = ("radius",)
 
 
 def grid(space: dict = SPACE) -> list[dict]:
@@ -42,7 +49,7 @@ def grid(space: dict = SPACE) -> list[dict]:
 
 def encode(cfgs: list[dict], space: dict = SPACE) -> np.ndarray:
     """Knob values on a log2 axis scaled to [0, 1] per knob (sweep_top 0, i.e. every start, sits at the
-    top of its axis, beyond the largest K; restarts R as 1 + R)."""
+    top of its axis, beyond the largest K; restarts R as 1 + R; the radius on a linear axis)."""
     cols = []
     for k, vals in space.items():
         if k == "sweep_top":
@@ -52,6 +59,8 @@ def encode(cfgs: list[dict], space: dict = SPACE) -> np.ndarray:
         elif k == "restarts":  # searched start sets 1 + R on the log2 axis
             f = lambda v: math.log2(1 + v)  # noqa: E731
             lo, hi = math.log2(1 + min(vals)), math.log2(1 + max(vals))
+        elif k in LINEAR_KNOBS:
+            f, lo, hi = float, float(min(vals)), float(max(vals))
         else:
             f, lo, hi = math.log2, math.log2(min(vals)), math.log2(max(vals))
         cols.append([(f(c[k]) - lo) / (hi - lo) if hi > lo else 0.0 for c in cfgs])
@@ -153,3 +162,57 @@ def random_search(evaluate, target: float, n: int, space: dict = SPACE, seed: in
 def best_feasible(hist: list[dict], target: float):
     ok = [h for h in hist if h["recall"] >= target]
     return min(ok, key=lambda h: h["cost"]) if ok else None
+
+
+class ScreenObjective:
+    """(cost, recall) of a knob configuration by real screens: cost = seconds per 1M ligands of the
+    screen (HIP events around a second run of the same screen), recall = the share of the reference
+    search's top fraction of the library (ties to the lower ligand) that the configuration's own top
+    fraction keeps.  Configurations are cached."""
+
+    def __init__(self, pocket_dev, lib_dev, reference, top_frac: float = 0.01, radius: float = 4.0):
+        self.dp, self.lib, self.frac, self.radius = pocket_dev, lib_dev, top_frac, radius
+        self.cache = {}
+        self.ref_seconds, ref = self.screen(reference)
+        self.ok = np.isfinite(ref)
+        self.ids = np.flatnonzero(self.ok)
+        self.k = max(1, int(round(top_frac * self.ok.sum())))
+        self.top_ref = set(self._top(ref).tolist())
+
+    def _top(self, best):
+        return self.ids[np.lexsort((self.ids, best[self.ok]))[:self.k]]
+
+    def screen(self, srch):
+        """Seconds of one screen and the per-ligand best scores."""
+        import torch
+
+        from . import pipeline as P
+        scr = P.Screener(self.dp, self.lib, P.DeviceSearch(srch))
+        scr.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        scr.run()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3, scr.best_score.cpu().numpy().astype(np.float64)
+
+    def search_of(self, cfg):
+        import dataclasses
+
+        from . import inputs as I
+        R = int(cfg.get("restarts", 0))
+        base = I.make_search(cfg["n_quat"], cfg["n_trans"], cfg["n_steps"], float(cfg.get("radius", self.radius)),
+                             self.dp.pocket.center)
+        return dataclasses.replace(base, sweep_top=int(cfg.get("sweep_top", 0)), passes=int(cfg.get("passes", 1)),
+                                   restarts=R, init_steps=I.restart_steps(R, cfg["n_steps"]) if R else None)
+
+    def recall_of(self, best) -> float:
+        return len(set(self._top(best).tolist()) & self.top_ref) / self.k
+
+    def __call__(self, cfg):
+        key = tuple(sorted(cfg.items()))
+        if key not in self.cache:
+            t, best = self.screen(self.search_of(cfg))
+            self.cache[key] = (t / self.lib.n_lig * 1e6, self.recall_of(best))
+        return self.cache[key]
