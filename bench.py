@@ -235,8 +235,10 @@ def prefilter_bench(args):
         how = (f"smallest with held-out recall >= {args.pf_target + args.pf_margin:.2f} "
                f"({len(sur.holdout_true)} held-out docked ligands)")
     log(f"docking the top {frac:.1%} by prediction ({how})")
+    fixed = args.pf_fixed_frac
     res = PF.filtered_screen(sur, dp, ds, W.dist, W.n_types, args.pf_lib, args.pf_chunk, frac,
-                             sample_every=args.pf_sample_every, log=log)
+                             sample_every=args.pf_sample_every, log=log,
+                             extra_fracs=(fixed,) if fixed > 0 and abs(fixed - frac) > 1e-9 else ())
     sid, ssc = res["sample_ids"], res["sample_scores"].astype(np.float64)
     recall = PF.recall_top(sid, ssc, res["selected_ids"], 0.01)
     fracs = [0.01, 0.02, 0.03, 0.05, 0.075, 0.1, 0.15, 0.2, 0.3]
@@ -244,6 +246,8 @@ def prefilter_bench(args):
     # the method without the network, at the same budgets: largest ligands first (ties by id), random
     size_rank = PF.ranks(-res["n_atoms"].astype(np.float64))[sid]
     curve_size = PF.recall_curve(size_rank, ssc, fracs + [frac], args.pf_lib)
+    small_rank = PF.ranks(res["n_atoms"].astype(np.float64))[sid]
+    curve_small = PF.recall_curve(small_rank, ssc, fracs + [frac], args.pf_lib)
     rng = np.random.default_rng(0)
     rand_rank = rng.permutation(args.pf_lib)[sid]
     curve_rand = PF.recall_curve(rand_rank, ssc, fracs + [frac], args.pf_lib)
@@ -272,10 +276,18 @@ def prefilter_bench(args):
         "speedup": (args.pf_lib / filtered_seconds) / plain_rate,
         "recall_curve": {f"{k:.3f}": v for k, v in curve.items()},
         "recall_curve_largest_first": {f"{k:.3f}": v for k, v in curve_size.items()},
+        "recall_curve_smallest_first": {f"{k:.3f}": v for k, v in curve_small.items()},
         "recall_curve_random": {f"{k:.3f}": v for k, v in curve_rand.items()},
         "host_generation_seconds": res["seconds_generate_on_host"],
         "n_sample": n_sample,
     }
+    for f, e in res["extra"].items():
+        fs = e["seconds_predict"] + e["seconds_dock_selected"]
+        out[f"fixed_fraction_{f:.3f}"] = {
+            "selected_fraction": f, "recall": PF.recall_top(sid, ssc, e["selected_ids"], 0.01),
+            "filtered_ligands_per_s": args.pf_lib / fs, "speedup": (args.pf_lib / fs) / plain_rate,
+            "filtered_seconds": fs, "seconds_dock_selected": e["seconds_dock_selected"],
+            "meets_target": PF.recall_top(sid, ssc, e["selected_ids"], 0.01) >= args.pf_target}
     print(json.dumps(out), flush=True)
 
 
@@ -668,7 +680,9 @@ def main():
     ap.add_argument("--pf-train", type=int, default=200_000)
     ap.add_argument("--pf-lib", type=int, default=10_000_000)
     ap.add_argument("--pf-chunk", type=int, default=1_000_000)
-    ap.add_argument("--pf-sample-every", type=int, default=50)
+    ap.add_argument("--pf-sample-every", type=int, default=20, help="recall sample: ids divisible by this")
+    ap.add_argument("--pf-fixed-frac", type=float, default=0.03,
+                    help="also dock this fixed top fraction from the same predictions (0: skip)")
     ap.add_argument("--pf-frac", type=float, default=0.0,
                     help="fraction docked after the filter; 0 = calibrated on the held-out docked ligands")
     ap.add_argument("--pf-target", type=float, default=0.95, help="recall of the true top 1%% to reach")

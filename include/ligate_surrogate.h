@@ -96,6 +96,14 @@ int surr_adam(const surr_model *m, float lr, float beta1, float beta2, float eps
 int surr_gather(const uint16_t *d_x, const float *d_t, const int32_t *d_idx, int64_t n_idx, int32_t row,
                 uint16_t *d_x_out, float *d_t_out, void *stream);
 
+/*
+ * Ensemble prediction (paper §3.5: the cheap model here is an ensemble of networks): d_out[i] =
+ * (d_y[0][i] + d_y[1][i] + ... + d_y[n_members-1][i]) / n_members, summed in member order in
+ * FP32.  d_y is [n_members][n] (each member's surr_forward output, rows contiguous).
+ * 1 <= n_members <= 64, n >= 0.
+ */
+int surr_average(const float *d_y, int32_t n_members, int64_t n, float *d_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

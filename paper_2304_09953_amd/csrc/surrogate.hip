@@ -130,7 +130,7 @@ __global__ void k_stats_final(const double *__restrict__ part, int n_chunks, int
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
-enum { EPI_F32 = 0, EPI_BIAS_RELU_BF16 = 1, EPI_MASK_BF16 = 2 };
+enum { EPI_F32 = 0, EPI_BIAS_RELU_BF16 = 1, EPI_MASK_BF16 = 2, EPI_HEAD = 3 };
 
 constexpr int kBM = 64, kBN = 64, kBK = 32, kPitch = kBK + 8;  // LDS rows padded against bank conflicts
 
@@ -205,6 +205,183 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
             Cb[(size_t)row * ldc + col] = bf2f(mask[(size_t)row * ldm + col]) > 0.0f ? f2bf(v) : (uint16_t)0;
         }
     }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Forward-layer GEMM, C = A B^T with A (M, K) and B (N, K) both K-contiguous (activations times
+// weights): 128 x 128 tiles per block of four wavefronts, each wavefront a 64 x 64 tile of 2 x 2
+// v_mfma_f32_32x32x16_bf16; K steps of 64 through two LDS buffers, the next step's operands loaded
+// from global memory into registers while the current step's MFMAs run, one barrier per step.
+// The MFMAs walk K in the same ascending 16-wide steps as k_gemm, so the results are identical.
+// Tiles are numbered so that each XCD (blocks are dealt to the eight XCDs in turn) takes a
+// contiguous run of them: the N tiles of one row block then run side by side in one L2.
+// Requires N % 128 == 0 and K % 64 == 0; rows m >= M are skipped.
+// Epilogues: EPI_BIAS_RELU_BF16 stores H = relu(C + bias) in BF16, staged through LDS so that
+// the stores are 16-byte and row-contiguous.  EPI_HEAD (the last hidden layer at inference)
+// stores nothing of H: each wavefront rounds its 64 x 64 tile of relu(C + bias) to BF16,
+// multiplies it by the output weights w3 and sums each row over its 64 columns in a fixed order,
+// writing part[row][2 (n tile) + wn]; k_head_sum adds the parts.
+// ---------------------------------------------------------------------------------------------
+
+constexpr int kTM = 128, kTN = 128, kTK = 64, kTP = kTK + 8;  // LDS pitch 144 B: conflict-free 16-B reads
+constexpr int kXcds = 8;
+
+template <int EPI>
+__global__ __launch_bounds__(256, 2) void k_gemm_nt(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
+                                                    const uint16_t *__restrict__ B, int ldb,
+                                                    uint16_t *__restrict__ Cb, int ldc,
+                                                    const float *__restrict__ bias, const uint16_t *__restrict__ w3,
+                                                    float *__restrict__ part) {
+    // two A buffers then two B buffers; after the K loop the head epilogue reuses the space
+    __shared__ __align__(16) uint16_t smem[4 * kTM * kTP];
+    static_assert(4 * 64 * kTP <= 4 * kTM * kTP, "output staging tile does not fit");
+    uint16_t(*As)[kTM * kTP] = reinterpret_cast<uint16_t(*)[kTM * kTP]>(smem);
+    uint16_t(*Bs)[kTN * kTP] = reinterpret_cast<uint16_t(*)[kTN * kTP]>(smem + 2 * kTM * kTP);
+    const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+    const int wm = w >> 1, wn = w & 1;
+    const int ntn = N / kTN;
+    const int nblk = (int)gridDim.x;
+    int tile = (int)blockIdx.x;
+    if (nblk % kXcds == 0) tile = (tile % kXcds) * (nblk / kXcds) + tile / kXcds;
+    const int m0 = (tile / ntn) * kTM, n0 = (tile % ntn) * kTN;
+
+    // global -> register staging: 128 rows x 64 k of A and of B in 16-byte chunks, four per thread
+    // (chunk c = t + 256 i: row c / 8, k offset 8 (c % 8)).  Rows of A past M read row M - 1 and
+    // are zeroed, so the loads carry no branch.
+    const int lrow = t >> 3, lk = (t & 7) * 8;
+    const uint16_t *ga[4], *gb[4];
+    uint32_t live[4];  // all ones for rows inside M, zero past it
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = lrow + 32 * i;
+        live[i] = m0 + row < M ? ~0u : 0u;
+        ga[i] = A + (size_t)min(m0 + row, M - 1) * lda + lk;
+        gb[i] = B + (size_t)(n0 + row) * ldb + lk;
+    }
+    auto masked = [](uint4 v, uint32_t mk) { return make_uint4(v.x & mk, v.y & mk, v.z & mk, v.w & mk); };
+    const int lofs = lrow * kTP + lk;
+    uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+#define LIGATE_GLOAD(k0)                                                              \
+    do {                                                                              \
+        ra0 = *reinterpret_cast<const uint4 *>(ga[0] + (k0));                        \
+        ra1 = *reinterpret_cast<const uint4 *>(ga[1] + (k0));                        \
+        ra2 = *reinterpret_cast<const uint4 *>(ga[2] + (k0));                        \
+        ra3 = *reinterpret_cast<const uint4 *>(ga[3] + (k0));                        \
+        rb0 = *reinterpret_cast<const uint4 *>(gb[0] + (k0));                        \
+        rb1 = *reinterpret_cast<const uint4 *>(gb[1] + (k0));                        \
+        rb2 = *reinterpret_cast<const uint4 *>(gb[2] + (k0));                        \
+        rb3 = *reinterpret_cast<const uint4 *>(gb[3] + (k0));                        \
+    } while (0)
+#define LIGATE_LSTORE(buf)                                                            \
+    do {                                                                              \
+        *reinterpret_cast<uint4 *>(&As[buf][lofs]) = masked(ra0, live[0]);            \
+        *reinterpret_cast<uint4 *>(&As[buf][lofs + 32 * kTP]) = masked(ra1, live[1]); \
+        *reinterpret_cast<uint4 *>(&As[buf][lofs + 64 * kTP]) = masked(ra2, live[2]); \
+        *reinterpret_cast<uint4 *>(&As[buf][lofs + 96 * kTP]) = masked(ra3, live[3]); \
+        *reinterpret_cast<uint4 *>(&Bs[buf][lofs]) = rb0;                             \
+        *reinterpret_cast<uint4 *>(&Bs[buf][lofs + 32 * kTP]) = rb1;                  \
+        *reinterpret_cast<uint4 *>(&Bs[buf][lofs + 64 * kTP]) = rb2;                  \
+        *reinterpret_cast<uint4 *>(&Bs[buf][lofs + 96 * kTP]) = rb3;                  \
+    } while (0)
+
+    f32x16 acc00, acc01, acc10, acc11;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc00[r] = acc01[r] = acc10[r] = acc11[r] = 0.0f;
+
+    LIGATE_GLOAD(0);
+    LIGATE_LSTORE(0);
+    __syncthreads();
+    const int nk = K / kTK;
+    for (int ks = 0; ks < nk; ++ks) {
+        const int cur = ks & 1;
+        if (ks + 1 < nk) LIGATE_GLOAD((ks + 1) * kTK);  // in flight during this step's MFMAs
+        const uint16_t *as = &As[cur][(wm * 64 + (lane & 31)) * kTP + 8 * (lane >> 5)];
+        const uint16_t *bs = &Bs[cur][(wn * 64 + (lane & 31)) * kTP + 8 * (lane >> 5)];
+#pragma unroll
+        for (int kk = 0; kk < kTK; kk += 16) {
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(as + kk);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(as + 32 * kTP + kk);
+            const bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(bs + kk);
+            const bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(bs + 32 * kTP + kk);
+            // operands swapped: each product is a 32 x 32 tile of C^T (the weights' rows first), so
+            // a lane ends up holding four consecutive columns of one row of C
+            acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0, a0, acc00, 0, 0, 0);
+            acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1, a0, acc01, 0, 0, 0);
+            acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0, a1, acc10, 0, 0, 0);
+            acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1, a1, acc11, 0, 0, 0);
+        }
+        // the other buffer was last read in the previous step, before its closing barrier
+        if (ks + 1 < nk) LIGATE_LSTORE(cur ^ 1);
+        __syncthreads();
+    }
+#undef LIGATE_GLOAD
+#undef LIGATE_LSTORE
+    const f32x16 acc[2][2] = {{acc00, acc01}, {acc10, acc11}};
+    // tile (i, j): lane holds row (lane & 31) of the i-th 32-row slice and, for q = 0..3, the columns
+    // 8 q + 4 (lane / 32) + 0..3 of the j-th 32-column slice, in acc[i][j][4 q + 0..3]
+    const int rl = lane & 31, ch = 4 * (lane >> 5);
+    if constexpr (EPI == EPI_HEAD) {
+        // each lane sums its 32 columns of a row (j, q, then the four columns), the two lanes that
+        // share a row add their sums, lower half first
+        float rs[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            float sum = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int col = n0 + wn * 64 + j * 32 + 8 * q + ch + u;
+                        sum += bf2f(f2bf(fmaxf(acc[i][j][4 * q + u] + bias[col], 0.0f))) * bf2f(w3[col]);
+                    }
+            const float other = __shfl_xor(sum, 32);
+            rs[i] = lane < 32 ? sum + other : other + sum;
+        }
+        if (lane < 32) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int row = m0 + wm * 64 + i * 32 + rl;
+                if (row < M) part[(size_t)row * (2 * ntn) + 2 * (tile % ntn) + wn] = rs[i];
+            }
+        }
+    } else {
+        // stage the wavefront's 64 x 64 BF16 tile in LDS (four columns per 8-byte write), then write
+        // it out in 16-byte pieces, eight lanes per 128-byte row segment
+        uint16_t *ct = smem + w * 64 * kTP;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int cl = j * 32 + 8 * q + ch, col = n0 + wn * 64 + cl;
+                    uint32_t h[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) h[u] = f2bf(fmaxf(acc[i][j][4 * q + u] + bias[col + u], 0.0f));
+                    *reinterpret_cast<uint2 *>(ct + (i * 32 + rl) * kTP + cl) =
+                        make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+                }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int c = lane + 64 * k, r = c >> 3, q8 = (c & 7) * 8;
+            const int row = m0 + wm * 64 + r;
+            const uint4 v = *reinterpret_cast<const uint4 *>(ct + r * kTP + q8);
+            if (row < M) *reinterpret_cast<uint4 *>(Cb + (size_t)row * ldc + n0 + wn * 64 + q8) = v;
+        }
+    }
+}
+
+// y[row] = (sum of the row's parts in order) + b3.
+__global__ void k_head_sum(const float *__restrict__ part, int n_part, int M, const float *__restrict__ b3,
+                           float *__restrict__ y) {
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= M) return;
+    float s = 0.0f;
+    for (int q = 0; q < n_part; ++q) s += part[(size_t)row * n_part + q];
+    y[row] = s + b3[0];
 }
 
 template <bool A_K, bool B_K, int EPI>
@@ -352,13 +529,22 @@ static FwdWs fwd_ws(const surr_model *m, int batch, void *ws) {
     return w;
 }
 
+// A forward layer: H = relu(X W^T + b) in BF16, on the large-tile kernel where the shape allows.
+static void forward_layer(hipStream_t st, int M, int N, int K, const uint16_t *X, const uint16_t *W, uint16_t *H,
+                          const float *bias) {
+    if (N % kTN == 0 && K % kTK == 0) {
+        const int64_t tiles = (int64_t)((M + kTM - 1) / kTM) * (N / kTN);
+        hipLaunchKernelGGL((k_gemm_nt<EPI_BIAS_RELU_BF16>), dim3((unsigned)tiles), dim3(256), 0, st, M, N, K, X, K, W,
+                           K, H, N, bias, (const uint16_t *)nullptr, (float *)nullptr);
+    } else {
+        gemm<true, true, EPI_BIAS_RELU_BF16>(st, M, N, K, X, K, W, K, nullptr, H, N, bias);
+    }
+}
+
 static void run_forward(const surr_model *m, const Layout &L, const uint16_t *x, int batch, const FwdWs &w,
                         hipStream_t st) {
-    const uint16_t *W1 = m->d_bf16 + L.bW1, *W2 = m->d_bf16 + L.bW2;
-    gemm<true, true, EPI_BIAS_RELU_BF16>(st, batch, m->h1, m->d_in, x, m->d_in, W1, m->d_in, nullptr, w.H1, m->h1,
-                                         m->d_master + L.b1);
-    gemm<true, true, EPI_BIAS_RELU_BF16>(st, batch, m->h2, m->h1, w.H1, m->h1, W2, m->h1, nullptr, w.H2, m->h2,
-                                         m->d_master + L.b2);
+    forward_layer(st, batch, m->h1, m->d_in, x, m->d_bf16 + L.bW1, w.H1, m->d_master + L.b1);
+    forward_layer(st, batch, m->h2, m->h1, w.H1, m->d_bf16 + L.bW2, w.H2, m->d_master + L.b2);
 }
 
 }  // namespace ligate
@@ -438,9 +624,23 @@ extern "C" int surr_forward(const surr_model *m, const uint16_t *d_x, int32_t ba
     hipStream_t st = (hipStream_t)stream;
     const Layout L = Layout::of(m->d_in, m->h1, m->h2);
     const FwdWs w = fwd_ws(m, batch, d_ws);
-    run_forward(m, L, d_x, batch, w, st);
-    hipLaunchKernelGGL(k_head, dim3((unsigned)batch), dim3(kWave), 0, st, w.H2, m->h2, m->d_bf16 + L.bw3,
-                       m->d_master + L.b3, batch, d_y, (const float *)nullptr, (float *)nullptr, (float *)nullptr);
+    if (m->h2 % kTN == 0 && m->h1 % kTK == 0) {
+        // inference: the output layer is fused into the last hidden layer's epilogue (H2 is never
+        // stored; the per-tile row sums go where H2 would be, 2 h2 / 128 floats per row)
+        forward_layer(st, batch, m->h1, m->d_in, d_x, m->d_bf16 + L.bW1, w.H1, m->d_master + L.b1);
+        const int ntn = m->h2 / kTN;
+        float *part = reinterpret_cast<float *>(w.H2);
+        const int64_t tiles = (int64_t)((batch + kTM - 1) / kTM) * ntn;
+        hipLaunchKernelGGL((k_gemm_nt<EPI_HEAD>), dim3((unsigned)tiles), dim3(256), 0, st, batch, m->h2, m->h1, w.H1,
+                           m->h1, m->d_bf16 + L.bW2, m->h1, (uint16_t *)nullptr, 0, m->d_master + L.b2,
+                           m->d_bf16 + L.bw3, part);
+        hipLaunchKernelGGL(k_head_sum, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, st, part, 2 * ntn, batch,
+                           m->d_master + L.b3, d_y);
+    } else {
+        run_forward(m, L, d_x, batch, w, st);
+        hipLaunchKernelGGL(k_head, dim3((unsigned)batch), dim3(kWave), 0, st, w.H2, m->h2, m->d_bf16 + L.bw3,
+                           m->d_master + L.b3, batch, d_y, (const float *)nullptr, (float *)nullptr, (float *)nullptr);
+    }
     return check_launch("surr_forward");
 }
 
@@ -546,4 +746,24 @@ extern "C" int surr_gather(const uint16_t *d_x, const float *d_t, const int32_t 
         hipLaunchKernelGGL(k_gather_f32, dim3((unsigned)((n_idx + 255) / 256)), dim3(256), 0, st, d_t, d_idx, n_idx,
                            d_t_out);
     return check_launch("surr_gather");
+}
+
+namespace ligate {
+__global__ void k_average(const float *__restrict__ y, int n_members, int64_t n, float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int m = 0; m < n_members; ++m) s += y[(int64_t)m * n + i];
+    out[i] = s / (float)n_members;
+}
+}  // namespace ligate
+
+extern "C" int surr_average(const float *d_y, int32_t n_members, int64_t n, float *d_out, void *stream) {
+    LIGATE_ABI_RANGE();
+    LIGATE_REQUIRE(n_members >= 1 && n_members <= 64 && n >= 0, DOCK_ERR_INVALID_ARG, "bad ensemble size");
+    if (n == 0) return DOCK_OK;
+    LIGATE_REQUIRE(d_y && d_out, DOCK_ERR_INVALID_ARG, "NULL array");
+    hipLaunchKernelGGL(k_average, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, d_y,
+                       n_members, n, d_out);
+    return check_launch("surr_average");
 }

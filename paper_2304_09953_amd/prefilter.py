@@ -16,9 +16,9 @@ resumes after the last finished unit, and its results equal an uninterrupted run
 is a pure function of seeded inputs and the state before it.  LIGATE_FAIL_AT makes a run raise before
 a named unit (the test hook of that path).
 
-Every computational step of a network runs in the library's kernels; this module orders the calls,
-moves ligand chunks between host and device, and does the host-side bookkeeping (the members' mean,
-validation error, ranks and recall).
+Every computational step of a network runs in the library's kernels, the members' mean included;
+this module orders the calls, moves ligand chunks between host and device, and does the host-side
+bookkeeping (validation error, ranks and recall).
 """
 from __future__ import annotations
 
@@ -117,8 +117,10 @@ class Surrogate:
     holdout_true: np.ndarray | None = None
 
     def predict_z(self, xb: torch.Tensor) -> np.ndarray:
-        """Mean of the members' outputs (z-scores of the best docking score) for BF16 features."""
-        return np.mean([m.predict(xb).cpu().numpy().astype(np.float64) for m in self.models], axis=0)
+        """Mean of the members' outputs (z-scores of the best docking score) for BF16 features, taken
+        on the device (surr_average)."""
+        ys = torch.stack([m.predict(xb) for m in self.models])
+        return SG.average(ys).cpu().numpy().astype(np.float64)
 
     def save(self, path: str) -> None:
         """Writes the trained filter to an .npz: each member's FP32 master weights and layer sizes, the
@@ -244,15 +246,21 @@ def train_surrogate(pocket_dev, search_dev, train_ligs, labels: np.ndarray | Non
 
 
 def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, n_lib: int, chunk: int, frac: float,
-                    stream: str = "lib", sample_every: int = 0, log=None, checkpoint_dir: str | None = None) -> dict:
+                    stream: str = "lib", sample_every: int = 0, log=None, checkpoint_dir: str | None = None,
+                    extra_fracs=()) -> dict:
     """Predicts every ligand of the streamed library and docks the global top `frac` by
     prediction.  With sample_every > 0 the ligands whose id is a multiple of it are also docked in
-    full during the same pass (the recall sample; timed separately).  With checkpoint_dir, finished
-    chunks are kept there and skipped on a rerun of the same run.  Returns ids, scores, timings
-    (timings cover the chunks computed in this call)."""
-    ck = Checkpoint(checkpoint_dir, {"kind": "screen", "n_lib": n_lib, "chunk": chunk, "frac": frac, "stream": stream,
-                                     "sample_every": sample_every, "n_types": n_types, "dist": repr(dist),
-                                     "filter": sur.fingerprint(), "search": search_dev.desc_fields()})
+    full during the same pass (the recall sample; timed separately).  Each fraction in extra_fracs
+    is selected from the same predictions and docked on its own, timed on its own
+    (out["extra"][f]).  With checkpoint_dir, finished chunks are kept there and skipped on a rerun
+    of the same run.  Returns ids, scores, timings (timings cover the chunks computed in this
+    call)."""
+    params = {"kind": "screen", "n_lib": n_lib, "chunk": chunk, "frac": frac, "stream": stream,
+              "sample_every": sample_every, "n_types": n_types, "dist": repr(dist),
+              "filter": sur.fingerprint(), "search": search_dev.desc_fields()}
+    if extra_fracs:
+        params["extra_fracs"] = [float(f) for f in extra_fracs]
+    ck = Checkpoint(checkpoint_dir, params)
     preds = np.empty(n_lib, dtype=np.float32)
     n_atoms = np.empty(n_lib, dtype=np.int16)
     t_gen = t_pred = t_sample = 0.0
@@ -288,36 +296,50 @@ def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, 
                 **({"sample_ids": s_ids[-1], "sample_scores": s_scores[-1]} if sample_every else {}))
         if log:
             log(f"predicted {s + ligs.n_lig}/{n_lib}" + (f", docked sample {sum(map(len, s_ids))}" if sample_every else ""))
-    n_sel = int(round(frac * n_lib))
-    p0 = time.perf_counter()
-    _, sel_ids = P.topk(torch.as_tensor(preds, device="cuda"), n_sel)
-    sel = np.sort(sel_ids.cpu().numpy().astype(np.int64))
-    t_pred += time.perf_counter() - p0
-    # dock the selection, regenerated chunk by chunk
-    scores = np.empty(len(sel), dtype=np.float32)
-    t_dock = 0.0
-    for ci, s in enumerate(range(0, n_lib, chunk)):
-        part = (sel >= s) & (sel < s + chunk)
-        if not part.any():
-            continue
-        done = ck.load(f"dock_{ci}")
-        if done is not None:
-            scores[part] = done["scores"]
-            continue
-        _fail_hook(f"dock:{ci}")
-        g0 = time.perf_counter()
-        ligs = library_chunk(dist, n_types, s, min(chunk, n_lib - s), stream).subset(sel[part] - s)
-        t_gen += time.perf_counter() - g0
-        torch.cuda.synchronize()
-        d0 = time.perf_counter()
-        scores[part] = P.screen(pocket_dev, P.DeviceLibrary(ligs), search_dev).best_score.cpu().numpy()
-        t_dock += time.perf_counter() - d0
-        ck.save(f"dock_{ci}", scores=scores[part])
-        if log:
-            log(f"docked selection up to id {s + chunk}")
+    pred_dev = torch.as_tensor(preds, device="cuda")
+
+    def select_and_dock(f: float, tag: str):
+        """The global top f by prediction, docked chunk by chunk; (ids, scores, select s, dock s, gen s)."""
+        n_sel = int(round(f * n_lib))
+        p0 = time.perf_counter()
+        _, sel_ids = P.topk(pred_dev, n_sel)
+        sel = np.sort(sel_ids.cpu().numpy().astype(np.int64))
+        t_sel = time.perf_counter() - p0
+        scores = np.empty(len(sel), dtype=np.float32)
+        t_dock = t_g = 0.0
+        for ci, s in enumerate(range(0, n_lib, chunk)):
+            part = (sel >= s) & (sel < s + chunk)
+            if not part.any():
+                continue
+            done = ck.load(f"dock{tag}_{ci}")
+            if done is not None:
+                scores[part] = done["scores"]
+                continue
+            _fail_hook(f"dock{tag}:{ci}")
+            g0 = time.perf_counter()
+            ligs = library_chunk(dist, n_types, s, min(chunk, n_lib - s), stream).subset(sel[part] - s)
+            t_g += time.perf_counter() - g0
+            torch.cuda.synchronize()
+            d0 = time.perf_counter()
+            scores[part] = P.screen(pocket_dev, P.DeviceLibrary(ligs), search_dev).best_score.cpu().numpy()
+            t_dock += time.perf_counter() - d0
+            ck.save(f"dock{tag}_{ci}", scores=scores[part])
+            if log:
+                log(f"docked the top {f:.1%} selection up to id {s + chunk}")
+        return sel, scores, t_sel, t_dock, t_g
+
+    sel, scores, t_sel, t_dock, t_g = select_and_dock(frac, "")
+    t_pred += t_sel
+    t_gen += t_g
     out = {"selected_ids": sel, "selected_scores": scores, "predictions": preds, "n_atoms": n_atoms,
            "seconds_predict": t_pred,
            "seconds_dock_selected": t_dock, "seconds_generate_on_host": t_gen, "n_selected": len(sel)}
+    out["extra"] = {}
+    for i, f in enumerate(extra_fracs):
+        e_sel, e_scores, e_tsel, e_tdock, e_tg = select_and_dock(float(f), f"x{i}")
+        out["extra"][float(f)] = {"selected_ids": e_sel, "selected_scores": e_scores,
+                                  "seconds_predict": t_pred - t_sel + e_tsel, "seconds_dock_selected": e_tdock,
+                                  "seconds_generate_on_host": e_tg, "n_selected": len(e_sel)}
     if sample_every:
         out.update(sample_ids=np.concatenate(s_ids), sample_scores=np.concatenate(s_scores),
                    seconds_dock_sample=t_sample)

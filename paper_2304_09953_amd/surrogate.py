@@ -14,7 +14,7 @@ from . import dock
 
 FEATURES = 512
 SURR_EXPORTS = ("surr_param_count", "surr_features", "surr_feature_stats", "surr_cast", "surr_forward",
-                "surr_backward", "surr_adam", "surr_gather")
+                "surr_backward", "surr_adam", "surr_gather", "surr_average")
 
 
 class SurrModel(ctypes.Structure):
@@ -40,6 +40,7 @@ def _lib():
         lib.surr_backward.argtypes = [P(SurrModel), vp, vp, i32, vp, vp, P(sz), vp]
         lib.surr_adam.argtypes = [P(SurrModel), f32, f32, f32, f32, i32, vp]
         lib.surr_gather.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp]
+        lib.surr_average.argtypes = [vp, i32, i64, vp, vp]
         for n in SURR_EXPORTS:
             getattr(lib, n).restype = ctypes.c_int
         _bound = True
@@ -180,3 +181,11 @@ def train(model: Model, X_bf16: torch.Tensor, t: torch.Tensor, epochs: int = 30,
         if log:
             log(f"epoch {ep + 1}/{epochs}: loss {hist[-1]:.4f}")
     return hist
+
+
+def average(ys: torch.Tensor, stream=None) -> torch.Tensor:
+    """Members' mean of predictions ys [n_members, n] (surr_average): [n] FP32."""
+    ys = ys.contiguous()
+    out = torch.empty(ys.shape[1], dtype=torch.float32, device=ys.device)
+    _check(_lib().surr_average(_p(ys), ys.shape[0], ys.shape[1], _p(out), _s(stream)), "surr_average")
+    return out

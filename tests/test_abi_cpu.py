@@ -76,6 +76,11 @@ def test_surrogate_argument_errors():
     assert lib.surr_forward(ctypes.byref(good), None, 8, None, None, ctypes.byref(sz), None) == 0
     assert lib.surr_backward(ctypes.byref(good), None, None, 30, None, None, ctypes.byref(sz), None) == -1
     assert lib.surr_features(None, None, None, None, 5, 10, 17, None, None, None, None, None) == -2
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.surr_average(fake, 0, 10, fake, None) == -1
+    assert lib.surr_average(fake, 65, 10, fake, None) == -1
+    assert lib.surr_average(None, 4, 10, fake, None) == -1
+    assert lib.surr_average(None, 4, 0, None, None) == 0
 
 
 def test_error_strings():

@@ -180,3 +180,18 @@ def test_training_overfits_a_small_set(env):
     assert hist[-1] < 0.1 * hist[0]
     y = m.predict(xb).cpu().numpy()
     assert S.r2(y, t) > 0.9
+
+
+def test_ensemble_average_on_the_device(env):
+    P, SG = env
+    rng = np.random.default_rng(8)
+    for m, n in ((1, 5), (4, 70001), (7, 1000)):
+        say(f"surr_average of {m} members x {n}")
+        y = rng.normal(size=(m, n)).astype(np.float32)
+        got = SG.average(torch.as_tensor(y).cuda()).cpu().numpy()
+        ref = y.astype(np.float64).mean(0)
+        assert np.allclose(got, ref, rtol=1e-6, atol=1e-6)
+        s = np.zeros(n, np.float32)
+        for k in range(m):  # the stated order: FP32 sums over members in order, then one division
+            s = (s + y[k]).astype(np.float32)
+        assert np.array_equal(got, (s / np.float32(m)).astype(np.float32))
