@@ -100,6 +100,8 @@ def summarize_counters(out_dir):
         "l1_to_l2_request_bytes": req_bytes,
         "l1_to_l2_bytes_per_launch": req * req_bytes,
         "l2_hit_rate": hit / (hit + miss),
+        "l2_hits_per_launch": hit,
+        "l2_misses_per_launch": miss,
         "valu_insts_per_launch": valu,
         "gpu_cycles_per_launch": gui / 8,
         "valu_busy": valu * 4 / (256 * 4) / (gui / 8),
@@ -804,6 +806,8 @@ def main():
         "frac": c["l1_to_l2_bytes_per_launch"] / t_screen / l2_peak if c else None,
         "algorithmic_frac": BYTES_PER_LOOKUP * lookups / t_screen / l2_peak,
         "l2_hit_rate": c["l2_hit_rate"] if c else None,
+        "l1_to_l2_requests_per_lookup": c["l1_to_l2_requests_per_launch"] / lookups if c else None,
+        "l2_misses_per_lookup": c["l2_misses_per_launch"] / lookups if c and "l2_misses_per_launch" in c else None,
         "hbm_side_bytes_per_s": c["hbm_bytes_per_launch"] / t_screen if c else None,
         "hbm_side_frac": c["hbm_bytes_per_launch"] / t_screen / 8e12 if c else None,
         "valu_busy": c["valu_busy"] if c else None,
