@@ -369,7 +369,8 @@ def batched_bench(args):
     # batched: one pack per chunk, four pockets per graph replay
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = Bt.screen_sites(dps, searches, ligs, k=k, chunk=args.chunk, tuned=True, use_graph=True, log=log)
+    res = Bt.screen_sites(dps, searches, ligs, k=k, chunk=args.chunk, tuned=args.launch_params == "tuned",
+                          use_graph=True, log=log)
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
     log(f"batched, shared pack: {t_batched:.1f} s, {len(dps) * n_lig / t_batched:.0f} pairs/s")
@@ -404,7 +405,8 @@ def batched_bench(args):
                       "unit": "pairs/s", "value": n_pairs / t_batched, "n_gpus": 1, "data": "synthetic",
                       "dtype": "f32",
                       "config": {"workload": (W.name if n_lig == W.n_lig else f"first {n_lig} ligands of " + W.name),
-                                 "chunk": args.chunk, "k": k, "tune_sample_per_bucket": args.tune_sample},
+                                 "chunk": args.chunk, "k": k, "tune_sample_per_bucket": args.tune_sample,
+                                 "launch_params": args.launch_params},
                       "batched_seconds": t_batched,
                       "persistent": {"pairs_per_s": n_pairs / t_pers, "seconds": t_pers,
                                      "library_upload_and_pack_seconds": t_upload,
@@ -706,8 +708,10 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="the 4-pocket workload through the autotuned, graph-replayed batching path")
     ap.add_argument("--chunk", type=int, default=16384, help="ligands per graph-replayed chunk (--batched)")
-    ap.add_argument("--tune-sample", type=int, default=256, help="ligands per size bucket timed by the autotuner")
+    ap.add_argument("--tune-sample", type=int, default=2048, help="ligands per size bucket timed by the autotuner")
     ap.add_argument("--tuning-out", default=None, help="also copy the autotuner table here (--batched)")
+    ap.add_argument("--launch-params", choices=("tuned", "library"), default="tuned",
+                    help="--batched: chunks use the autotuned launch parameters, or the library's own choice")
     ap.add_argument("--budget-curve", action="store_true",
                     help="speed and quality of the search-budget variants (sweep_top, passes) against the full "
                          "search on --n-lig ligands (default 20000)")

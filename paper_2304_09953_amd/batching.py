@@ -3,7 +3,10 @@
 Ligands are clustered by size into buckets; each bucket is screened in chunks of fixed capacity
 whose launch parameters (rigid starts per work item, wavefronts per block) come from the
 autotuner, and each chunk's pack -> screen -> top-k merge sequence is captured once into a
-hipGraph and replayed with the next chunk's ligands copied into the same device buffers.  Every
+hipGraph and replayed with the next chunk's ligands copied into the same device buffers.  The
+next chunk is prepared on the host in pinned memory while the device works on the current one
+and is copied with stream-ordered asynchronous copies; results stay on the device until the
+bucket ends.  Every
 step runs in the library's kernels through the C ABI; this module only orders the calls, owns the
 buffers and times candidate launch parameters.
 """
@@ -22,7 +25,14 @@ from . import pipeline as P
 
 TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
 BUCKET_EDGES = (25, 41, 71)  # atom-count buckets: <= 24, 25-40, 41-70, >= 71
-CANDIDATES = [(p, w) for p in (32, 64, 128, 256) for w in (1, 2, 4, 8) if p >= w]
+# Autotuned: wavefronts per block.  Rigid starts per work item follow the library's device model
+# (0: enough items for every compute unit's resident blocks to take four times over, at most 256
+# per item), evaluated for the chunk actually launched.  Timings only carry over to a chunk when
+# the sample is large enough to get the chunk's item size (256 starts, from about 1k ligands at
+# 8192 starts on 256 compute units): on 256-ligand samples both the item size and the wavefronts
+# per block picked were 1-3 % slower on 16k-ligand chunks of the four-pocket workload.
+CANDIDATES = [(0, w) for w in (2, 4, 8)]
+TUNE_SAMPLE = 2048  # ligands per size bucket
 
 
 def size_bucket(n_atoms: np.ndarray) -> np.ndarray:
@@ -61,9 +71,10 @@ def time_screen(pocket_dev, lib_dev, search, starts_per_item: int, waves_per_blo
     return float(np.median(ts))
 
 
-def autotune(pocket_dev, ligs, search, per_bucket: int = 256, log=None) -> dict:
+def autotune(pocket_dev, ligs, search, per_bucket: int = TUNE_SAMPLE, log=None) -> dict:
     """Times every candidate (starts per item, waves per block) on a sample of each size bucket
-    and keeps the fastest.  Returns {bucket: {"starts_per_item", "waves_per_block", "s_per_ligand",
+    and keeps the fastest (starts per item 0 = the library's device model, applied at run time to
+    the launched chunk).  Returns {bucket: {"starts_per_item", "waves_per_block", "s_per_ligand",
     "candidates": {...}}}."""
     b = size_bucket(ligs.n_atoms)
     out = {}
@@ -115,6 +126,62 @@ def lookup(arch: str, dims, S: int, bucket: int, path: str | None = None) -> tup
 class ChunkShape:
     n_lig: int      # ligand capacity of a chunk
     n_atoms: int    # atom capacity of a chunk
+
+
+class ChunkStaging:
+    """Pinned host copies of one chunk's inputs.  A chunk is written here on the host while the
+    device still works on the previous chunk, then copied with stream-ordered asynchronous copies,
+    so host preparation overlaps device work.  Reusing a staging area waits for its last copies."""
+
+    def __init__(self, shape: ChunkShape):
+        L, A = shape.n_lig, shape.n_atoms
+        self.shape = shape
+        pin = {"pin_memory": True}
+        self.atom_off = torch.empty(L + 1, dtype=torch.int32, **pin)
+        self.bond_off = torch.empty(L + 1, dtype=torch.int32, **pin)
+        self.xyz = torch.empty(3 * A, dtype=torch.float32, **pin)
+        self.types = torch.empty(A, dtype=torch.uint8, **pin)
+        self.bonds = torch.empty(2 * max(A, 1), dtype=torch.int32, **pin)
+        self.rot = torch.empty(max(A, 1), dtype=torch.uint8, **pin)
+        self.gid = torch.empty(L, dtype=torch.int32, **pin)
+        self.event = None
+        self.n = self.a = self.e = 0
+
+    def fill(self, ligs, ids: np.ndarray):
+        L, A = self.shape.n_lig, self.shape.n_atoms
+        n, a, e = ligs.n_lig, int(ligs.atom_off[-1]), int(ligs.bond_off[-1])
+        assert n <= L and a <= A, (n, a, L, A)
+        if self.event is not None:
+            self.event.synchronize()  # the copies out of this area have finished
+        off = self.atom_off.numpy()
+        off[:n + 1] = ligs.atom_off
+        off[n + 1:] = a  # unused slots: empty ligands (status n_atoms, score +inf)
+        boff = self.bond_off.numpy()
+        boff[:n + 1] = ligs.bond_off
+        boff[n + 1:] = e
+        self.xyz.numpy()[:3 * a] = ligs.xyz.reshape(-1)
+        self.types.numpy()[:a] = ligs.types
+        if e:
+            self.bonds.numpy()[:2 * e] = ligs.bonds.reshape(-1)
+            self.rot.numpy()[:e] = ligs.rot
+        gid = self.gid.numpy()
+        gid[:n] = ids
+        gid[n:] = 2 ** 31 - 1
+        self.n, self.a, self.e = n, a, e
+
+    def upload(self, dst) -> None:
+        """Asynchronous copies into a pipeline's input buffers (on the current stream, so after the
+        work already queued there, which may still read the previous chunk)."""
+        dst.atom_off.copy_(self.atom_off, non_blocking=True)
+        dst.bond_off.copy_(self.bond_off, non_blocking=True)
+        dst.xyz[:3 * self.a].copy_(self.xyz[:3 * self.a], non_blocking=True)
+        dst.types[:self.a].copy_(self.types[:self.a], non_blocking=True)
+        if self.e:
+            dst.bonds[:2 * self.e].copy_(self.bonds[:2 * self.e], non_blocking=True)
+            dst.rot[:self.e].copy_(self.rot[:self.e], non_blocking=True)
+        dst.set_ids(self.gid)
+        self.event = torch.cuda.Event()
+        self.event.record()
 
 
 class ChunkPipeline:
@@ -199,6 +266,9 @@ class ChunkPipeline:
         gid[:n] = ids
         self.ids[self.k:].copy_(torch.from_numpy(gid))
 
+    def set_ids(self, gid_pinned: torch.Tensor):
+        self.ids[self.k:].copy_(gid_pinned, non_blocking=True)
+
     def run(self):
         if self.graph is not None:
             self.graph.replay()
@@ -229,16 +299,22 @@ def screen_buckets(pocket_dev, search, ligs, k: int = 1000, chunk: int = 16384, 
         if len(idx) == 0:
             continue
         p, w = lookup(arch, pocket_dev.pocket.dims, search.n_steps, bucket, table_path) if tuned else (0, 0)
-        pipe = ChunkPipeline(pocket_dev, search, chunk_shape_for(ligs, idx, chunk), ligs.n_types, k, p, w, use_graph)
+        shape = chunk_shape_for(ligs, idx, chunk)
+        pipe = ChunkPipeline(pocket_dev, search, shape, ligs.n_types, k, p, w, use_graph)
         pipe.reset()
         pipe.scores[:k].copy_(torch.from_numpy(top_s))
         pipe.ids[:k].copy_(torch.from_numpy(top_i))
+        staging = [ChunkStaging(shape), ChunkStaging(shape)]
+        bucket_best = torch.empty(len(idx), dtype=torch.float32, device=pipe.scores.device)
         t0 = time.perf_counter()
-        for s in range(0, len(idx), chunk):
+        for c, s in enumerate(range(0, len(idx), chunk)):
             sel = idx[s:s + chunk]
-            pipe.load(ligs.subset(sel), ligs.ids[sel].astype(np.int32))
+            st = staging[c % 2]
+            st.fill(ligs.subset(sel), ligs.ids[sel].astype(np.int32))  # overlaps the previous chunk
+            st.upload(pipe)
             pipe.run()
-            best[sel] = pipe.scores[k:k + len(sel)].cpu().numpy()
+            bucket_best[s:s + len(sel)].copy_(pipe.scores[k:k + len(sel)])
+        best[idx] = bucket_best.cpu().numpy()
         torch.cuda.synchronize()
         top_s = pipe.scores[:k].cpu().numpy()
         top_i = pipe.ids[:k].cpu().numpy()
@@ -367,6 +443,11 @@ class SitesChunkPipeline:
         self.ids[:, self.k:].copy_(g.unsqueeze(0).expand(self.n_p, L))
         self.site_ids[self.k:].copy_(g)
 
+    def set_ids(self, gid_pinned: torch.Tensor):
+        L = self.shape.n_lig
+        self.site_ids[self.k:].copy_(gid_pinned, non_blocking=True)
+        self.ids[:, self.k:].copy_(self.site_ids[self.k:].unsqueeze(0).expand(self.n_p, L))
+
     def run(self):
         if self.graph is not None:
             self.graph.replay()
@@ -402,17 +483,25 @@ def screen_sites(pockets_dev, searches, ligs, k: int = 1000, chunk: int = 16384,
             continue
         params = [lookup(arch, dp.pocket.dims, s.n_steps, bucket, table_path) if tuned else (0, 0)
                   for dp, s in zip(pockets_dev, searches)]
-        pipe = SitesChunkPipeline(pockets_dev, searches, chunk_shape_for(ligs, idx, chunk), ligs.n_types, k, params,
-                                  use_graph)
+        shape = chunk_shape_for(ligs, idx, chunk)
+        pipe = SitesChunkPipeline(pockets_dev, searches, shape, ligs.n_types, k, params, use_graph)
         pipe.reset()
         pipe.seed(tops, site_top)
+        staging = [ChunkStaging(shape), ChunkStaging(shape)]
+        dev = pipe.scores.device
+        bucket_best = torch.empty((n_p, len(idx)), dtype=torch.float32, device=dev)
+        bucket_site = torch.empty(len(idx), dtype=torch.int32, device=dev)
         t0 = time.perf_counter()
-        for s in range(0, len(idx), chunk):
+        for c, s in enumerate(range(0, len(idx), chunk)):
             sel = idx[s:s + chunk]
-            pipe.load(ligs.subset(sel), ligs.ids[sel].astype(np.int32))
+            st = staging[c % 2]
+            st.fill(ligs.subset(sel), ligs.ids[sel].astype(np.int32))  # overlaps the previous chunk
+            st.upload(pipe)
             pipe.run()
-            best[:, sel] = pipe.scores[:, k:k + len(sel)].cpu().numpy()
-            site[sel] = pipe.site[k:k + len(sel)].cpu().numpy()
+            bucket_best[:, s:s + len(sel)].copy_(pipe.scores[:, k:k + len(sel)])
+            bucket_site[s:s + len(sel)].copy_(pipe.site[k:k + len(sel)])
+        best[:, idx] = bucket_best.cpu().numpy()
+        site[idx] = bucket_site.cpu().numpy()
         torch.cuda.synchronize()
         tops = [(pipe.scores[p, :k].cpu().numpy(), pipe.ids[p, :k].cpu().numpy()) for p in range(n_p)]
         site_top = (pipe.site_scores[:k].cpu().numpy(), pipe.site_ids[:k].cpu().numpy())
