@@ -442,17 +442,29 @@ __global__ void k_head_back(const uint16_t *__restrict__ H2, const uint16_t *__r
     dH2[i] = bf2f(H2[i]) > 0.0f ? f2bf(dy[b] * bf2f(w3[k])) : (uint16_t)0;
 }
 
-// out[c] = sum_r wgt[r] X[r][c] (wgt == NULL: plain sum), rows in order.
-__global__ void k_colsum(const uint16_t *__restrict__ X, int rows, int cols, const float *__restrict__ wgt,
-                         float *__restrict__ out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
+// out[c] = sum_r wgt[r] X[r][c] (wgt == NULL: plain sum).  A block takes 64 columns; its four
+// wavefronts take the rows r = g, g + 4, g + 8, ... (g = wavefront), each in order, and the four
+// partial sums are added in wavefront order: a fixed order, with coalesced 128-byte row reads.
+constexpr int kColGroups = 4;
+__global__ __launch_bounds__(kWave *kColGroups) void k_colsum(const uint16_t *__restrict__ X, int rows, int cols,
+                                                             const float *__restrict__ wgt,
+                                                             float *__restrict__ out) {
+    __shared__ float part[kColGroups][kWave];
+    const int g = threadIdx.x / kWave, lane = lane_id(), c = blockIdx.x * kWave + lane;
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r) {
-        const float v = bf2f(X[(size_t)r * cols + c]);
-        s = wgt ? fmaf(wgt[r], v, s) : s + v;
+    if (c < cols) {
+        for (int r = g; r < rows; r += kColGroups) {
+            const float v = bf2f(X[(size_t)r * cols + c]);
+            s = wgt ? fmaf(wgt[r], v, s) : s + v;
+        }
     }
-    out[c] = s;
+    part[g][lane] = s;
+    __syncthreads();
+    if (g == 0 && c < cols) {
+        float t = part[0][lane];
+        for (int q = 1; q < kColGroups; ++q) t += part[q][lane];
+        out[c] = t;
+    }
 }
 
 __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
@@ -677,20 +689,20 @@ extern "C" int surr_backward(const surr_model *m, const uint16_t *d_x, const flo
                        m->d_master + L.b3, batch, (float *)nullptr, d_t, r2, dy);
     hipLaunchKernelGGL(k_loss, dim3(1), dim3(kWave), 0, st, r2, dy, batch, d_loss, g + L.b3);
     // output layer
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((m->h2 + 255) / 256)), dim3(256), 0, st, w.H2, batch, m->h2, dy,
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((m->h2 + kWave - 1) / kWave)), dim3(kWave * kColGroups), 0, st, w.H2, batch, m->h2, dy,
                        g + L.w3);
     const int64_t n2 = (int64_t)batch * m->h2;
     hipLaunchKernelGGL(k_head_back, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, w.H2, m->d_bf16 + L.bw3, dy,
                        batch, m->h2, dH2);
     // second layer: dW2 = dH2^T H1, db2 = column sums of dH2, dH1 = (dH2 W2) where H1 > 0
     gemm<false, false, EPI_F32>(st, m->h2, m->h1, batch, dH2, m->h2, w.H1, m->h1, g + L.W2, nullptr, m->h1);
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((m->h2 + 255) / 256)), dim3(256), 0, st, dH2, batch, m->h2,
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((m->h2 + kWave - 1) / kWave)), dim3(kWave * kColGroups), 0, st, dH2, batch, m->h2,
                        (const float *)nullptr, g + L.b2);
     gemm<true, false, EPI_MASK_BF16>(st, batch, m->h1, m->h2, dH2, m->h2, m->d_bf16 + L.bW2, m->h1, nullptr, dH1,
                                      m->h1, nullptr, w.H1, m->h1);
     // first layer: dW1 = dH1^T x, db1 = column sums of dH1
     gemm<false, false, EPI_F32>(st, m->h1, m->d_in, batch, dH1, m->h1, d_x, m->d_in, g + L.W1, nullptr, m->d_in);
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((m->h1 + 255) / 256)), dim3(256), 0, st, dH1, batch, m->h1,
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((m->h1 + kWave - 1) / kWave)), dim3(kWave * kColGroups), 0, st, dH1, batch, m->h1,
                        (const float *)nullptr, g + L.b1);
     return check_launch("surr_backward");
 }

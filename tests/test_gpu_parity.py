@@ -447,16 +447,20 @@ def test_pocket96_lib100k_sample_full_search(P):
 
 
 @pytest.mark.timeout(600)
-def test_pockets4_heavy_tail_on_the_128_pocket(P):
-    """The 250k-ligand workload's largest pocket (128^3 x 16 types) with two of its heavy-tail
-    ligands (80-120 atoms), full 8192-start search, against the oracle on its own 128^3 grid."""
+@pytest.mark.parametrize("pi,pick", [(3, "heavy"), (1, "mixed")])
+def test_pockets4_pockets_against_the_oracle(P, pi, pick):
+    """Pockets of the 250k-ligand workload against the oracle on their own grids, full 8192-start
+    search: the largest (128^3 x 16 types) with two heavy-tail ligands (80-120 atoms), and the 80^3
+    pocket with one heavy-tail and two typical ligands."""
     W = I.workload("pockets4-lib250k")
-    pocket = W.pockets[3]
-    assert pocket.dims == (128, 128, 128)
+    pocket = W.pockets[pi]
+    assert pocket.dims == ((128, 128, 128) if pi == 3 else (80, 80, 80))
     lib_all = W.ligands(n_lig=2000)
-    heavy = np.flatnonzero((lib_all.n_atoms >= 80) & (lib_all.n_rot >= 4))[:2]
-    ligs = lib_all.subset(heavy)
-    say(f"pockets4 128^3 pocket, heavy ligands {heavy.tolist()} (n {ligs.n_atoms.tolist()}, "
+    heavy = np.flatnonzero((lib_all.n_atoms >= 80) & (lib_all.n_rot >= 4))
+    typical = np.flatnonzero((np.abs(lib_all.n_atoms - 35) <= 3) & (lib_all.n_rot == 5))
+    sel = heavy[:2] if pick == "heavy" else np.sort(np.r_[heavy[2:3], typical[:2]])
+    ligs = lib_all.subset(sel)
+    say(f"pockets4 {pocket.dims[0]}^3 pocket, ligands {sel.tolist()} (n {ligs.n_atoms.tolist()}, "
         f"B {ligs.n_rot.tolist()}), full search")
     dp = P.DevicePocket(pocket)
     g = _screen(P, dp, ligs, W.search, start_scores=True)
@@ -465,8 +469,8 @@ def test_pockets4_heavy_tail_on_the_128_pocket(P):
     e = check_exact_and_valid(pocket, G, ligs, W.search, sel, g["score"], g["start"], g["steps"])
     orc = oracle.dock(pocket, G, ligs, W.search, per_start=True)
     n_div = check_optimal(pocket, G, ligs, W.search, sel, g["score"], g["start"], orc, g["finals"], g["start_steps"])
-    say(f"128^3 heavy: rescoring max rel err {e:.3g}, best {g['score'].tolist()} vs oracle {orc['best'].tolist()}, "
-        f"{n_div} split at near-ties")
+    say(f"{pocket.dims[0]}^3: rescoring max rel err {e:.3g}, best {g['score'].tolist()} vs oracle "
+        f"{orc['best'].tolist()}, {n_div} split at near-ties")
 
 
 @pytest.mark.parametrize("S", [300, 1024])
