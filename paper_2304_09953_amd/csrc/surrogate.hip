@@ -374,6 +374,210 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt(int M, int N, int K, const u
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Forward-layer GEMM for the network's own widths (K = 512 or 1024, N a multiple of BN), with the
+// operands copied from global memory straight into LDS (global_load_lds_dwordx4: no register
+// staging, no LDS store instructions) through a three-stage ring of K steps of 32, so that two K
+// steps are in flight while a third is multiplied.
+// * Block tile 128 x BN, four wavefronts of 64 x BN/2, each 2 x BN/64 v_mfma_f32_32x32x16_bf16
+//   tiles, operands swapped as in k_gemm_nt (a lane holds four consecutive columns of one row).
+//   The K order of every accumulator is that of k_gemm_nt, so the products are identical.
+// * A stage holds the A rows then the B rows, 64 bytes each; 16-byte chunk c of row r sits in
+//   slot c ^ (((r >> 1) ^ (r >> 3)) & 3), which keeps the fragment reads free of bank conflicts.
+//   Lane i of a copy instruction writes LDS bytes [16 i, 16 i + 16) of its 1 KB piece, so each
+//   lane fetches the global chunk that belongs in that slot.
+// * Each stage is a separate LDS array and the K loop is unrolled, so the compiler can tell the
+//   copies into one stage from the fragment reads of another and adds no waits of its own; the
+//   waits are explicit: before step k a wavefront waits until only its copies of step k + 1 are
+//   outstanding, then all wavefronts meet at a barrier (after their LDS reads have completed,
+//   since the copy issued next overwrites the stage read in the step before).
+// * Rows of A past M load row M - 1 (finite values whose results are never stored).
+// Epilogues as in k_gemm_nt: EPI_BIAS_RELU_BF16 stages relu(C + bias) in BF16 through LDS (two
+// halves of 32 rows) for 16-byte row-contiguous stores; EPI_HEAD multiplies the BF16 tile by w3
+// and writes per-row sums, part[row][2 (n tile) + wn], each over the wavefront's BN/2 columns.
+// ---------------------------------------------------------------------------------------------
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// s_waitcnt vmcnt(n), leaving the other counters alone (n is a constant once the caller's loop is
+// unrolled, so the switch folds to one instruction)
+__device__ __forceinline__ void wait_vmcnt(int n) {
+#define LIGATE_VMCNT(v) \
+    case v: __builtin_amdgcn_s_waitcnt(((v) & 15) | (7 << 4) | (15 << 8) | (((v) >> 4) << 14)); break;
+    switch (n) {
+        LIGATE_VMCNT(0) LIGATE_VMCNT(1) LIGATE_VMCNT(2) LIGATE_VMCNT(3) LIGATE_VMCNT(4) LIGATE_VMCNT(5)
+        LIGATE_VMCNT(6) LIGATE_VMCNT(7) LIGATE_VMCNT(8)
+        default: __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8)); break;
+    }
+#undef LIGATE_VMCNT
+}
+
+__device__ __forceinline__ int ring_swizzle(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+constexpr int kRingBK = 32, kRingStages = 3;
+
+template <int EPI, int BN, int NK>
+__global__ __launch_bounds__(256, BN == 128 ? 3 : 2) void k_gemm_lds(int M, int N, const uint16_t *__restrict__ A,
+                                                                     const uint16_t *__restrict__ B,
+                                                                     uint16_t *__restrict__ Cb,
+                                                                     const float *__restrict__ bias,
+                                                                     const uint16_t *__restrict__ w3,
+                                                                     float *__restrict__ part) {
+    constexpr int BK = kRingBK, NS = kRingStages, CH = BK / 8;
+    constexpr int STAGE = (kTM + BN) * BK;      // BF16 values per stage
+    constexpr int WN = BN / 2, NJ = WN / 32;    // columns per wavefront, 32-wide MFMA tiles along them
+    constexpr int LA = kTM * CH / 256, LB = BN * CH / 256, LPW = LA + LB;  // copies per wavefront per stage
+    constexpr int K = NK * BK;
+    static_assert(2 * 32 * WN <= STAGE, "output staging does not fit a stage");
+    __shared__ __align__(16) uint16_t s0[STAGE];
+    __shared__ __align__(16) uint16_t s1[STAGE];
+    __shared__ __align__(16) uint16_t s2[STAGE];
+    __shared__ __align__(16) float sbias[BN];
+    __shared__ __align__(16) uint16_t sw3[EPI == EPI_HEAD ? BN : 8];
+    uint16_t *const stg[NS] = {s0, s1, s2};
+    const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+    const int wm = w >> 1, wn = w & 1;
+    const int ntn = N / BN;
+    const int nblk = (int)gridDim.x;
+    int tile = (int)blockIdx.x;
+    if (nblk % kXcds == 0) tile = (tile % kXcds) * (nblk / kXcds) + tile / kXcds;
+    const int m0 = (tile / ntn) * kTM, n0 = (tile % ntn) * BN;
+
+    // the global chunk each lane copies, per copy instruction: piece p = w L + q of the A (B) rows
+    const uint16_t *ga[LA], *gb[LB];
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+        const int P = (w * LA + q) * kWave + lane, r = P / CH, c = (P % CH) ^ ring_swizzle(r);
+        ga[q] = A + (size_t)min(m0 + r, M - 1) * K + c * 8;
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+        const int P = (w * LB + q) * kWave + lane, r = P / CH, c = (P % CH) ^ ring_swizzle(r);
+        gb[q] = B + (size_t)(n0 + r) * K + c * 8;
+    }
+    auto issue = [&](int ks, int buf) {
+        uint16_t *base = stg[buf];
+#pragma unroll
+        for (int q = 0; q < LA; ++q)
+            __builtin_amdgcn_global_load_lds((const void *)(ga[q] + ks * BK), (lds_void *)(base + (w * LA + q) * 512),
+                                             16, 0, 0);
+#pragma unroll
+        for (int q = 0; q < LB; ++q)
+            __builtin_amdgcn_global_load_lds((const void *)(gb[q] + ks * BK),
+                                             (lds_void *)(base + kTM * BK + (w * LB + q) * 512), 16, 0, 0);
+    };
+
+    f32x16 acc[2][NJ];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    // bias (and the BF16 w3) of the tile's columns, copied into LDS ahead of the ring's first stages
+    // (so the waits for those stages cover them too) and read after the ring's first barrier
+    if (w < BN / kWave)
+        __builtin_amdgcn_global_load_lds((const void *)(bias + n0 + kWave * w + lane), (lds_void *)(sbias + kWave * w),
+                                         4, 0, 0);
+    if constexpr (EPI == EPI_HEAD) {
+        if (w < BN / (2 * kWave))  // pairs of BF16 values as 4-byte words
+            __builtin_amdgcn_global_load_lds((const void *)(reinterpret_cast<const uint32_t *>(w3 + n0) + kWave * w + lane),
+                                             (lds_void *)(sw3 + 2 * kWave * w), 4, 0, 0);
+    }
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s) issue(s, s);
+    const int fl = ring_swizzle(lane & 31);  // rows read by this lane differ by multiples of 32
+    const int arow = (wm * 64 + (lane & 31)) * BK, brow = kTM * BK + (wn * WN + (lane & 31)) * BK;
+#pragma unroll
+    for (int ks0 = 0; ks0 < NK; ks0 += NS) {
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            const int ks = ks0 + st;
+            if (ks >= NK) break;
+            const int ahead = NK - 1 - ks;  // copies of later steps already issued: min(ahead, NS - 2) steps
+            wait_vmcnt(LPW * (ahead < NS - 2 ? ahead : NS - 2));
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            if (ks + NS - 1 < NK) issue(ks + NS - 1, (st + NS - 1) % NS);
+            const uint16_t *S = stg[st];
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 16) {
+                const int off = (((kk >> 3) + (lane >> 5)) ^ fl) << 3;
+                bf16x8 a[2], b[NJ];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(S + arow + i * 32 * BK + off);
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(S + brow + j * 32 * BK + off);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+    // tile (i, j): lane holds row i 32 + (lane & 31) and, for q = 0..3, the columns j 32 + 8 q +
+    // 4 (lane / 32) + 0..3 of the wavefront's columns, in acc[i][j][4 q + 0..3]
+    const int rl = lane & 31, ch = 4 * (lane >> 5);
+    if constexpr (EPI == EPI_HEAD) {
+        // each lane sums its columns of a row (j, q, then the four columns), the two lanes that share
+        // a row add their sums, lower half first
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            float sum = 0.0f;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int cl = wn * WN + j * 32 + 8 * q + ch;
+                    const float4 bb = *reinterpret_cast<const float4 *>(sbias + cl);
+                    const uint2 ww = *reinterpret_cast<const uint2 *>(sw3 + cl);
+                    sum += bf2f(f2bf(fmaxf(acc[i][j][4 * q + 0] + bb.x, 0.0f))) * bf2f((uint16_t)ww.x);
+                    sum += bf2f(f2bf(fmaxf(acc[i][j][4 * q + 1] + bb.y, 0.0f))) * bf2f((uint16_t)(ww.x >> 16));
+                    sum += bf2f(f2bf(fmaxf(acc[i][j][4 * q + 2] + bb.z, 0.0f))) * bf2f((uint16_t)ww.y);
+                    sum += bf2f(f2bf(fmaxf(acc[i][j][4 * q + 3] + bb.w, 0.0f))) * bf2f((uint16_t)(ww.y >> 16));
+                }
+            const float other = __shfl_xor(sum, 32);
+            const float rs = lane < 32 ? sum + other : other + sum;
+            const int row = m0 + wm * 64 + i * 32 + rl;
+            if (lane < 32 && row < M) part[(size_t)row * (2 * ntn) + 2 * (tile % ntn) + wn] = rs;
+        }
+    } else {
+        // per half i: each wavefront stages its 32 x WN BF16 tile (rows of 2 WN bytes, 16-byte chunk c
+        // of row r in slot c ^ (r & 7)) in s0 (wavefronts 0, 1) or s1 (2, 3), then stores it in
+        // 16-byte row-contiguous pieces
+        constexpr int RC = WN / 8;
+        wait_vmcnt(0);
+        __syncthreads();  // the ring is no longer read
+        uint16_t *ct = (w < 2 ? s0 : s1) + (w & 1) * 32 * WN;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int cl = j * 32 + 8 * q + ch;
+                    const float4 bb = *reinterpret_cast<const float4 *>(sbias + wn * WN + cl);
+                    const uint32_t h0 = f2bf(fmaxf(acc[i][j][4 * q + 0] + bb.x, 0.0f));
+                    const uint32_t h1 = f2bf(fmaxf(acc[i][j][4 * q + 1] + bb.y, 0.0f));
+                    const uint32_t h2 = f2bf(fmaxf(acc[i][j][4 * q + 2] + bb.z, 0.0f));
+                    const uint32_t h3 = f2bf(fmaxf(acc[i][j][4 * q + 3] + bb.w, 0.0f));
+                    *reinterpret_cast<uint2 *>(ct + rl * WN + (((cl >> 3) ^ (rl & 7)) << 3) + ch) =
+                        make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
+                }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < RC / 2; ++k) {
+                const int c = lane + kWave * k, r = c / RC, cc = c % RC;
+                const int row = m0 + wm * 64 + i * 32 + r;
+                const uint4 v = *reinterpret_cast<const uint4 *>(ct + r * WN + ((cc ^ (r & 7)) << 3));
+                if (row < M) *reinterpret_cast<uint4 *>(Cb + (size_t)row * N + n0 + wn * WN + cc * 8) = v;
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // y[row] = (sum of the row's parts in order) + b3.
 __global__ void k_head_sum(const float *__restrict__ part, int n_part, int M, const float *__restrict__ b3,
                            float *__restrict__ y) {
@@ -542,9 +746,19 @@ static FwdWs fwd_ws(const surr_model *m, int batch, void *ws) {
 }
 
 // A forward layer: H = relu(X W^T + b) in BF16, on the large-tile kernel where the shape allows.
+static unsigned lds_tiles(int M, int N, int BN) { return (unsigned)((int64_t)((M + kTM - 1) / kTM) * (N / BN)); }
+
 static void forward_layer(hipStream_t st, int M, int N, int K, const uint16_t *X, const uint16_t *W, uint16_t *H,
                           const float *bias) {
-    if (N % kTN == 0 && K % kTK == 0) {
+    const uint16_t *no_w3 = nullptr;
+    float *no_part = nullptr;
+    if (N % 128 == 0 && K == 512) {
+        hipLaunchKernelGGL((k_gemm_lds<EPI_BIAS_RELU_BF16, 128, 16>), dim3(lds_tiles(M, N, 128)), dim3(256), 0, st, M,
+                           N, X, W, H, bias, no_w3, no_part);
+    } else if (N % 128 == 0 && K == 1024) {
+        hipLaunchKernelGGL((k_gemm_lds<EPI_BIAS_RELU_BF16, 128, 32>), dim3(lds_tiles(M, N, 128)), dim3(256), 0, st, M,
+                           N, X, W, H, bias, no_w3, no_part);
+    } else if (N % kTN == 0 && K % kTK == 0) {
         const int64_t tiles = (int64_t)((M + kTM - 1) / kTM) * (N / kTN);
         hipLaunchKernelGGL((k_gemm_nt<EPI_BIAS_RELU_BF16>), dim3((unsigned)tiles), dim3(256), 0, st, M, N, K, X, K, W,
                            K, H, N, bias, (const uint16_t *)nullptr, (float *)nullptr);
@@ -638,15 +852,23 @@ extern "C" int surr_forward(const surr_model *m, const uint16_t *d_x, int32_t ba
     const FwdWs w = fwd_ws(m, batch, d_ws);
     if (m->h2 % kTN == 0 && m->h1 % kTK == 0) {
         // inference: the output layer is fused into the last hidden layer's epilogue (H2 is never
-        // stored; the per-tile row sums go where H2 would be, 2 h2 / 128 floats per row)
+        // stored; the per-tile row sums go where H2 would be, at most 2 h2 / 128 floats per row)
         forward_layer(st, batch, m->h1, m->d_in, d_x, m->d_bf16 + L.bW1, w.H1, m->d_master + L.b1);
-        const int ntn = m->h2 / kTN;
         float *part = reinterpret_cast<float *>(w.H2);
-        const int64_t tiles = (int64_t)((batch + kTM - 1) / kTM) * ntn;
-        hipLaunchKernelGGL((k_gemm_nt<EPI_HEAD>), dim3((unsigned)tiles), dim3(256), 0, st, batch, m->h2, m->h1, w.H1,
-                           m->h1, m->d_bf16 + L.bW2, m->h1, (uint16_t *)nullptr, 0, m->d_master + L.b2,
-                           m->d_bf16 + L.bw3, part);
-        hipLaunchKernelGGL(k_head_sum, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, st, part, 2 * ntn, batch,
+        int n_part;
+        if (m->h2 % 256 == 0 && m->h1 == 1024) {
+            n_part = 2 * (m->h2 / 256);
+            hipLaunchKernelGGL((k_gemm_lds<EPI_HEAD, 256, 32>), dim3(lds_tiles(batch, m->h2, 256)), dim3(256), 0, st,
+                               batch, m->h2, w.H1, m->d_bf16 + L.bW2, (uint16_t *)nullptr, m->d_master + L.b2,
+                               m->d_bf16 + L.bw3, part);
+        } else {
+            n_part = 2 * (m->h2 / kTN);
+            const int64_t tiles = (int64_t)((batch + kTM - 1) / kTM) * (m->h2 / kTN);
+            hipLaunchKernelGGL((k_gemm_nt<EPI_HEAD>), dim3((unsigned)tiles), dim3(256), 0, st, batch, m->h2, m->h1,
+                               w.H1, m->h1, m->d_bf16 + L.bW2, m->h1, (uint16_t *)nullptr, 0, m->d_master + L.b2,
+                               m->d_bf16 + L.bw3, part);
+        }
+        hipLaunchKernelGGL(k_head_sum, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, st, part, n_part, batch,
                            m->d_master + L.b3, d_y);
     } else {
         run_forward(m, L, d_x, batch, w, st);
