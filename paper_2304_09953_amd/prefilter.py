@@ -247,24 +247,34 @@ def train_surrogate(pocket_dev, search_dev, train_ligs, labels: np.ndarray | Non
 
 def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, n_lib: int, chunk: int, frac: float,
                     stream: str = "lib", sample_every: int = 0, log=None, checkpoint_dir: str | None = None,
-                    extra_fracs=()) -> dict:
+                    extra_fracs=(), cascade_search=None, cascade_pools=(), cascade_final: float = 0.03) -> dict:
     """Predicts every ligand of the streamed library and docks the global top `frac` by
     prediction.  With sample_every > 0 the ligands whose id is a multiple of it are also docked in
     full during the same pass (the recall sample; timed separately).  Each fraction in extra_fracs
     is selected from the same predictions and docked on its own, timed on its own
-    (out["extra"][f]).  With checkpoint_dir, finished chunks are kept there and skipped on a rerun
-    of the same run.  Returns ids, scores, timings (timings cover the chunks computed in this
-    call)."""
+    (out["extra"][f]).
+
+    Cascade (with cascade_search, a cheaper search budget, and cascade_pools): for each pool
+    fraction p, the top p by prediction is docked with cascade_search, and the top cascade_final of
+    the library by those scores (taken from the pool) is docked in full (out["cascade"][p]).  The
+    recall sample is then also docked with cascade_search (out["sample_cheap_scores"]).
+
+    With checkpoint_dir, finished chunks are kept there and skipped on a rerun of the same run.
+    Returns ids, scores, timings (timings cover the chunks computed in this call)."""
     params = {"kind": "screen", "n_lib": n_lib, "chunk": chunk, "frac": frac, "stream": stream,
               "sample_every": sample_every, "n_types": n_types, "dist": repr(dist),
               "filter": sur.fingerprint(), "search": search_dev.desc_fields()}
     if extra_fracs:
         params["extra_fracs"] = [float(f) for f in extra_fracs]
+    if cascade_search is not None and cascade_pools:
+        params["cascade"] = {"search": cascade_search.desc_fields(), "pools": [float(f) for f in cascade_pools],
+                             "final": float(cascade_final)}
+    cascade = cascade_search is not None and len(cascade_pools) > 0
     ck = Checkpoint(checkpoint_dir, params)
     preds = np.empty(n_lib, dtype=np.float32)
     n_atoms = np.empty(n_lib, dtype=np.int16)
-    t_gen = t_pred = t_sample = 0.0
-    s_ids, s_scores = [], []
+    t_gen = t_pred = t_sample = t_sample_cheap = 0.0
+    s_ids, s_scores, s_cheap = [], [], []
     for ci, s in enumerate(range(0, n_lib, chunk)):
         done = ck.load(f"predict_{ci}")
         if done is not None:
@@ -273,6 +283,8 @@ def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, 
             if sample_every:
                 s_ids.append(done["sample_ids"])
                 s_scores.append(done["sample_scores"])
+                if cascade:
+                    s_cheap.append(done["sample_cheap"])
             continue
         _fail_hook(f"predict:{ci}")
         g0 = time.perf_counter()
@@ -283,6 +295,7 @@ def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, 
         preds[s:s + ligs.n_lig] = sur.predict_library(P.DeviceLibrary(ligs))
         t_pred += time.perf_counter() - p0
         n_atoms[s:s + ligs.n_lig] = ligs.n_atoms
+        extra = {}
         if sample_every:
             loc = np.flatnonzero(ligs.ids % sample_every == 0)
             sub = ligs.subset(loc)
@@ -291,20 +304,20 @@ def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, 
             s_scores.append(P.screen(pocket_dev, P.DeviceLibrary(sub), search_dev).best_score.cpu().numpy())
             t_sample += time.perf_counter() - d0
             s_ids.append(sub.ids)
+            extra = {"sample_ids": s_ids[-1], "sample_scores": s_scores[-1]}
+            if cascade:
+                d0 = time.perf_counter()
+                s_cheap.append(P.screen(pocket_dev, P.DeviceLibrary(sub), cascade_search).best_score.cpu().numpy())
+                t_sample_cheap += time.perf_counter() - d0
+                extra["sample_cheap"] = s_cheap[-1]
         e = s + ligs.n_lig
-        ck.save(f"predict_{ci}", preds=preds[s:e], n_atoms=n_atoms[s:e],
-                **({"sample_ids": s_ids[-1], "sample_scores": s_scores[-1]} if sample_every else {}))
+        ck.save(f"predict_{ci}", preds=preds[s:e], n_atoms=n_atoms[s:e], **extra)
         if log:
             log(f"predicted {s + ligs.n_lig}/{n_lib}" + (f", docked sample {sum(map(len, s_ids))}" if sample_every else ""))
     pred_dev = torch.as_tensor(preds, device="cuda")
 
-    def select_and_dock(f: float, tag: str):
-        """The global top f by prediction, docked chunk by chunk; (ids, scores, select s, dock s, gen s)."""
-        n_sel = int(round(f * n_lib))
-        p0 = time.perf_counter()
-        _, sel_ids = P.topk(pred_dev, n_sel)
-        sel = np.sort(sel_ids.cpu().numpy().astype(np.int64))
-        t_sel = time.perf_counter() - p0
+    def dock_ids(sel: np.ndarray, search, tag: str, what: str):
+        """Docks the ligands `sel` (sorted ids) chunk by chunk with `search`; (scores, dock s, gen s)."""
         scores = np.empty(len(sel), dtype=np.float32)
         t_dock = t_g = 0.0
         for ci, s in enumerate(range(0, n_lib, chunk)):
@@ -321,11 +334,24 @@ def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, 
             t_g += time.perf_counter() - g0
             torch.cuda.synchronize()
             d0 = time.perf_counter()
-            scores[part] = P.screen(pocket_dev, P.DeviceLibrary(ligs), search_dev).best_score.cpu().numpy()
+            scores[part] = P.screen(pocket_dev, P.DeviceLibrary(ligs), search).best_score.cpu().numpy()
             t_dock += time.perf_counter() - d0
             ck.save(f"dock{tag}_{ci}", scores=scores[part])
             if log:
-                log(f"docked the top {f:.1%} selection up to id {s + chunk}")
+                log(f"docked {what} up to id {s + chunk}")
+        return scores, t_dock, t_g
+
+    def top_ids(keys_dev: torch.Tensor, k: int, ids_dev: torch.Tensor | None = None):
+        """The k lowest keys (ties to the lower id) on the device; (sorted ids, seconds)."""
+        p0 = time.perf_counter()
+        _, sel_ids = P.topk(keys_dev, k, ids_dev)
+        sel = np.sort(sel_ids.cpu().numpy().astype(np.int64))
+        return sel, time.perf_counter() - p0
+
+    def select_and_dock(f: float, tag: str):
+        """The global top f by prediction, docked chunk by chunk; (ids, scores, select s, dock s, gen s)."""
+        sel, t_sel = top_ids(pred_dev, int(round(f * n_lib)))
+        scores, t_dock, t_g = dock_ids(sel, search_dev, tag, f"the top {f:.1%} selection")
         return sel, scores, t_sel, t_dock, t_g
 
     sel, scores, t_sel, t_dock, t_g = select_and_dock(frac, "")
@@ -340,9 +366,25 @@ def filtered_screen(sur: Surrogate, pocket_dev, search_dev, dist, n_types: int, 
         out["extra"][float(f)] = {"selected_ids": e_sel, "selected_scores": e_scores,
                                   "seconds_predict": t_pred - t_sel + e_tsel, "seconds_dock_selected": e_tdock,
                                   "seconds_generate_on_host": e_tg, "n_selected": len(e_sel)}
+    out["cascade"] = {}
+    if cascade:
+        k_final = int(round(cascade_final * n_lib))
+        for i, f in enumerate(cascade_pools):
+            pool, t_pool_sel = top_ids(pred_dev, int(round(float(f) * n_lib)))
+            cheap, t_pool, t_g1 = dock_ids(pool, cascade_search, f"c{i}", f"the top {float(f):.1%} pool (budget)")
+            final, t_fin_sel = top_ids(torch.as_tensor(cheap, device="cuda"), min(k_final, len(pool)),
+                                       torch.as_tensor(pool.astype(np.int32), device="cuda"))
+            full, t_fin, t_g2 = dock_ids(final, search_dev, f"cf{i}", f"the cascade's top {cascade_final:.1%}")
+            out["cascade"][float(f)] = {
+                "pool_ids": pool, "pool_cheap_scores": cheap, "selected_ids": final, "selected_scores": full,
+                "seconds_predict": t_pred - t_sel + t_pool_sel, "seconds_dock_pool": t_pool,
+                "seconds_select_final": t_fin_sel, "seconds_dock_selected": t_fin,
+                "seconds_generate_on_host": t_g1 + t_g2, "n_pool": len(pool), "n_selected": len(final)}
     if sample_every:
         out.update(sample_ids=np.concatenate(s_ids), sample_scores=np.concatenate(s_scores),
                    seconds_dock_sample=t_sample)
+        if cascade:
+            out.update(sample_cheap_scores=np.concatenate(s_cheap), seconds_dock_sample_cheap=t_sample_cheap)
     return out
 
 
@@ -372,6 +414,29 @@ def calibrate_fraction(pred: np.ndarray, true: np.ndarray, target: float, top: f
     curve = recall_curve(r, true, grid, len(pred), top)
     for f in grid:
         if curve[float(f)] >= target:
+            return float(f)
+    return 1.0
+
+
+def cascade_recall(pred: np.ndarray, cheap: np.ndarray, true: np.ndarray, pool: float, final: float,
+                   top: float = 0.01) -> float:
+    """Recall of the true top `top` of a docked set when the top `pool` by prediction is docked with a
+    cheaper search and the top `final` of the set by those scores (taken from the pool) is kept.
+    Ties go to the lower index, as in dock_topk."""
+    n = len(true)
+    k = max(1, int(round(top * n)))
+    best = set(np.lexsort((np.arange(n), true))[:k].tolist())
+    in_pool = np.flatnonzero(ranks(pred) < int(round(pool * n)))
+    kept = in_pool[np.lexsort((in_pool, cheap[in_pool]))[:int(round(final * n))]]
+    return len(best & set(kept.tolist())) / k
+
+
+def calibrate_cascade(pred: np.ndarray, cheap: np.ndarray, true: np.ndarray, final: float, target: float,
+                      top: float = 0.01, grid=np.round(np.arange(0.01, 1.0001, 0.01), 3)) -> float:
+    """Smallest pool fraction whose cascade recall on a docked held-out set reaches `target` (1.0 if
+    none does)."""
+    for f in grid:
+        if f >= final and cascade_recall(pred, cheap, true, float(f), final, top) >= target:
             return float(f)
     return 1.0
 

@@ -63,6 +63,33 @@ def test_filtered_screen_selects_by_prediction_and_docks_like_plain(trained):
     assert r == c[0.2]
 
 
+def test_cascade_selects_by_budget_scores_and_docks_like_plain(trained):
+    import dataclasses
+    P, PF, W, dp, ds, ligs, sur = trained
+    cs = P.DeviceSearch(dataclasses.replace(W.search, sweep_top=256))
+    say("cascade on a 3000-ligand library: top 20 % by prediction docked with the best 256 rigid starts swept, "
+        "then the top 3 % by those scores docked in full")
+    res = PF.filtered_screen(sur, dp, ds, W.dist, W.n_types, 3000, 1000, 0.1, stream="sample", sample_every=3,
+                             cascade_search=cs, cascade_pools=(0.2,), cascade_final=0.03)
+    c = res["cascade"][0.2]
+    ids = np.arange(3000)
+    pool = np.sort(np.lexsort((ids, res["predictions"]))[:600])
+    assert np.array_equal(c["pool_ids"], pool)
+    lib = I.make_ligands(3000, W.dist, W.n_types, stream="sample")
+    cheap = P.screen(dp, P.DeviceLibrary(lib), cs).best_score.cpu().numpy()
+    assert np.array_equal(c["pool_cheap_scores"], cheap[pool])
+    final = np.sort(pool[np.lexsort((pool, cheap[pool]))[:90]])
+    assert np.array_equal(c["selected_ids"], final)
+    plain = P.screen(dp, P.DeviceLibrary(lib), ds).best_score.cpu().numpy()
+    assert np.array_equal(c["selected_scores"], plain[final])
+    assert np.array_equal(res["sample_cheap_scores"], cheap[::3])
+    # the held-out form of the same cascade, on all 3000 ligands, reproduces the recall of the selection
+    sel = set(final.tolist())
+    full_casc = PF.cascade_recall(res["predictions"].astype(np.float64), cheap.astype(np.float64),
+                                  plain.astype(np.float64), 0.2, 0.03, top=0.01)
+    assert full_casc == np.mean([i in sel for i in np.lexsort((ids, plain))[:30]])
+
+
 def test_filtered_screen_resumes_after_a_failure(trained, tmp_path, monkeypatch):
     P, PF, W, dp, ds, ligs, sur = trained
     args = (sur, dp, ds, W.dist, W.n_types, 2500, 1000, 0.2)

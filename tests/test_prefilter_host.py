@@ -41,6 +41,32 @@ def test_calibrate_fraction():
     assert PF.calibrate_fraction(-true, true, 0.95) == 1.0
 
 
+def test_cascade_recall_and_its_calibration():
+    rng = np.random.default_rng(2)
+    n = 2000
+    true = rng.normal(size=n)
+    # a perfect budgeted docking: the pool alone decides, and the final cut keeps all of the top it holds
+    pred = true + rng.normal(scale=0.5, size=n)
+    in_pool = PF.ranks(pred) < 400
+    best = np.argsort(true, kind="stable")[:20]
+    assert PF.cascade_recall(pred, true, true, 0.2, 0.03) == np.mean(in_pool[best])
+    # a perfect prediction: the budgeted scores alone decide, within the first 3 %
+    cheap = true + rng.normal(scale=0.5, size=n)
+    assert PF.cascade_recall(true, cheap, true, 1.0, 0.03) == np.mean(PF.ranks(cheap)[best] < 60)
+    # a pool smaller than the final cut keeps only the pool
+    assert PF.cascade_recall(true, cheap, true, 0.005, 0.03) == 0.5
+    # tie order: equal budgeted scores go to the lower index
+    flat = np.zeros(n)
+    kept = np.sort(np.flatnonzero(in_pool))[:60]
+    assert PF.cascade_recall(pred, flat, true, 0.2, 0.03) == np.mean(np.isin(best, kept))
+    # calibration: the smallest pool on the grid that reaches the target, 1.0 when none does
+    f = PF.calibrate_cascade(pred, cheap, true, 0.03, 0.8)
+    assert 0.03 < f < 1.0
+    assert PF.cascade_recall(pred, cheap, true, f, 0.03) >= 0.8
+    assert PF.cascade_recall(pred, cheap, true, round(f - 0.01, 3), 0.03) < 0.8
+    assert PF.calibrate_cascade(-true, -true, true, 0.03, 0.5) == 1.0
+
+
 def test_checkpoint_round_trip_and_manifest(tmp_path):
     d = str(tmp_path / "ck")
     params = {"kind": "screen", "n_lib": 10, "frac": 0.25, "search": {"n_steps": 8, "starts": "ab"}}
