@@ -238,24 +238,44 @@ def prefilter_bench(args):
                f"({len(sur.holdout_true)} held-out docked ligands)")
     log(f"docking the top {frac:.1%} by prediction ({how})")
     fixed = args.pf_fixed_frac
-    cascade_ds, pools, cascade_how = None, (), None
-    if args.pf_cascade_top > 0 and fixed > 0:
+    cascade_ds, pools, cascade_how, cascade_top, candidates = None, (), None, 0, []
+    tops = [int(v) for v in args.pf_cascade_tops.split(",") if v.strip()] if args.pf_cascade_tops else []
+    if tops and fixed > 0:
         # cascade: the pool by prediction, docked with a smaller search budget, then the fixed top fraction of
-        # the library by those scores docked in full; the pool is calibrated on the held-out ligands
+        # the library by those scores docked in full.  For each budget (rigid starts swept) the pool is the
+        # smallest reaching the target on the held-out ligands; the budget with the lowest estimated time
+        # (pool at the budget's held-out rate + the fixed fraction at the plain rate of the label docking) runs.
         import dataclasses
-        cs = dataclasses.replace(W.search, sweep_top=args.pf_cascade_top, passes=args.pf_cascade_passes)
-        cascade_ds = P.DeviceSearch(cs)
+        import torch
         n_hold = len(sur.holdout_true)
         hold = train.subset(np.arange(args.pf_train - n_hold, args.pf_train))
-        cheap_hold = P.screen(dp, P.DeviceLibrary(hold), cascade_ds).best_score.cpu().numpy().astype(np.float64)
-        pool = PF.calibrate_cascade(sur.holdout_pred, cheap_hold, sur.holdout_true, fixed,
-                                    args.pf_target + args.pf_margin)
-        pools = (pool,)
-        cascade_how = (f"pool = smallest with held-out cascade recall >= {args.pf_target + args.pf_margin:.2f}; "
-                       f"held-out recall of the budgeted docking alone at {fixed:.0%}: "
-                       f"{PF.recall_curve(PF.ranks(cheap_hold), sur.holdout_true, [fixed], n_hold)[fixed]:.3f}")
-        log(f"cascade: pool {pool:.0%} docked with the best {args.pf_cascade_top} rigid starts swept "
-            f"({args.pf_cascade_passes} pass), then the top {fixed:.0%} in full ({cascade_how})")
+        hold_dev = P.DeviceLibrary(hold)
+        plain_est = args.pf_train / sur.metrics["label_seconds"]
+        best = None
+        for k in tops:
+            cds = P.DeviceSearch(dataclasses.replace(W.search, sweep_top=k, passes=args.pf_cascade_passes))
+            P.screen(dp, P.DeviceLibrary(hold.subset(np.arange(min(2000, n_hold)))), cds)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cheap_hold = P.screen(dp, hold_dev, cds).best_score.cpu().numpy().astype(np.float64)
+            rate = n_hold / (time.perf_counter() - t0)
+            pool = PF.calibrate_cascade(sur.holdout_pred, cheap_hold, sur.holdout_true, fixed,
+                                        args.pf_target + args.pf_margin)
+            est = args.pf_lib * (pool / rate + fixed / plain_est)
+            alone = PF.recall_curve(PF.ranks(cheap_hold), sur.holdout_true, [fixed], n_hold)[fixed]
+            candidates.append({"sweep_top": k, "pool_fraction": pool, "held_out_budget_ligands_per_s": rate,
+                               "held_out_recall_of_budget_alone": alone, "estimated_seconds": est})
+            log(f"cascade candidate: best {k} rigid starts swept, pool {pool:.0%}, held-out budget rate "
+                f"{rate:.0f}/s, estimated {est:.1f} s")
+            if pool < 1.0 and (best is None or est < best[0]):
+                best = (est, k, pool, cds)
+        if best is not None:
+            _, cascade_top, pool, cascade_ds = best
+            pools = (pool,)
+            cascade_how = (f"budget and pool = the fastest estimate among {tops} rigid starts swept, each with the "
+                           f"smallest pool reaching held-out cascade recall >= {args.pf_target + args.pf_margin:.2f}")
+            log(f"cascade: pool {pool:.0%} docked with the best {cascade_top} rigid starts swept "
+                f"({args.pf_cascade_passes} pass), then the top {fixed:.0%} in full")
     res = PF.filtered_screen(sur, dp, ds, W.dist, W.n_types, args.pf_lib, args.pf_chunk, frac,
                              sample_every=args.pf_sample_every, log=log,
                              extra_fracs=(fixed,) if fixed > 0 and abs(fixed - frac) > 1e-9 else (),
@@ -318,10 +338,11 @@ def prefilter_bench(args):
         no_net = PF.recall_curve(PF.ranks(res["sample_cheap_scores"].astype(np.float64)), ssc, [fixed], n_sample)[fixed]
         no_net_s = args.pf_lib / cheap_rate + fixed * args.pf_lib / plain_rate
         out["cascade"] = {
-            "what": (f"top {f:.0%} by prediction docked with the best {args.pf_cascade_top} of "
+            "what": (f"top {f:.0%} by prediction docked with the best {cascade_top} of "
                      f"{W.search.n_starts} rigid starts swept ({args.pf_cascade_passes} pass); the top {fixed:.0%} "
                      f"of the library by those scores docked in full"),
-            "calibration": cascade_how, "pool_fraction": f, "docked_in_full_fraction": fixed,
+            "calibration": cascade_how, "candidates": candidates, "sweep_top": cascade_top,
+            "pool_fraction": f, "docked_in_full_fraction": fixed,
             "recall": rec, "meets_target": rec >= args.pf_target,
             "filtered_ligands_per_s": args.pf_lib / fs, "speedup": (args.pf_lib / fs) / plain_rate,
             "filtered_seconds": fs, "seconds_predict": c["seconds_predict"],
@@ -776,8 +797,9 @@ def main():
     ap.add_argument("--pf-margin", type=float, default=0.02, help="added to the target when calibrating")
     ap.add_argument("--pf-epochs", type=int, default=20, help="most epochs per member (early stopping)")
     ap.add_argument("--pf-members", type=int, default=4, help="networks in the ensemble")
-    ap.add_argument("--pf-cascade-top", type=int, default=1024,
-                    help="cascade: rigid starts swept in the pool's budgeted docking (0: no cascade)")
+    ap.add_argument("--pf-cascade-tops", default="256,512,1024,2048",
+                    help="cascade: candidate numbers of rigid starts swept in the pool's budgeted docking, "
+                         "comma-separated ('' = no cascade)")
     ap.add_argument("--pf-cascade-passes", type=int, default=1, help="cascade: greedy passes of the budgeted docking")
     ap.add_argument("--surrogate-roofline", action="store_true",
                     help="MFMA throughput of the pre-filter network's forward pass and training step")
