@@ -210,6 +210,17 @@ __device__ __forceinline__ bool mask_has(const uint4 &m, int i) {
     return (w >> (i & 31)) & 1u;
 }
 
+// The mask with atom i's bit cleared (i wave-uniform).
+__device__ __forceinline__ uint4 mask_without(uint4 m, int i) {
+    const uint32_t keep = ~(1u << (i & 31));
+    const int w = i >> 5;
+    m.x &= w == 0 ? keep : ~0u;
+    m.y &= w == 1 ? keep : ~0u;
+    m.z &= w == 2 ? keep : ~0u;
+    m.w &= w == 3 ? keep : ~0u;
+    return m;
+}
+
 // mask_has for atom lane + 64 h of a wavefront (lane < 64; h is 0 or 1, usually a constant of an
 // unrolled loop), selecting between two words instead of four.
 __device__ __forceinline__ bool mask_has_lane(const uint4 &m, int h, int lane) {

@@ -550,7 +550,8 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
             const TorRec tr = L.tor[k];
             float xax, xay, xaz, ux, uy, uz;
             axis_lds(tr, W, xax, xay, xaz, ux, uy, uz);
-            turn_torsion<APL>(W, n, make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]), xax, xay, xaz,
+            turn_torsion<APL>(W, n, mask_without(make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]), tr.b),
+                              xax, xay, xaz,
                               ux, uy, uz, st, cs, sn);
         }
         if (turned) E = direct_score_lds<BOUNDARY, LAYOUT>(g, rs, s, L, W);
@@ -567,7 +568,11 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
     // the sweeps of all passes: torsion k runs 0..B-1 in every pass
     for (int sweep = 0, k = 0; sweep < s.passes * L.B; ++sweep, k = k + 1 == L.B ? 0 : k + 1) {
         const TorRec tr = L.tor[k];
+        // the moving side; its atom b lies on the axis, so its position, its grid term and its distances
+        // to every other atom stay the same through the sweep: only the other moving atoms are turned
+        // and scored, and b is neither moving nor fixed for the clash pairs
         const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
+        const uint4 turn = mask_without(mask, tr.b);
         float xax, xay, xaz, ux, uy, uz;
         axis_lds(tr, W, xax, xay, xaz, ux, uy, uz);
 
@@ -615,7 +620,7 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
         for (int h = 0; h < 2; ++h) {
             if (kWave * h >= n) break;
             const int i = lane + kWave * h;
-            const bool mv = i < n && mask_has_lane(mask, h, lane);
+            const bool mv = i < n && mask_has_lane(turn, h, lane);
             const uint64_t bal = __ballot(mv);
             const int cnt = __popcll(bal);
             if (mv) {
@@ -751,7 +756,7 @@ __device__ float run_start(const GridC &g, rsrc_t rs, const SearchC &s, const Li
         Emax = fmaxf(Emax, fabsf(E));
 
         // apply the winning step
-        turn_torsion<APL>(W, n, mask, xax, xay, xaz, ux, uy, uz, sbest, cs, sn);
+        turn_torsion<APL>(W, n, turn, xax, xay, xaz, ux, uy, uz, sbest, cs, sn);
         if (lane == k) {  // total turn of torsion k over the passes, modulo S
             my_step += sbest;
             my_step -= my_step >= s.S ? s.S : 0;
@@ -771,7 +776,8 @@ __device__ __forceinline__ void build_pose(const GridC &g, const SearchC &s, con
     place(g, s, L, e % s.QT, cx, cy, cz);
     for (int k = 0; k < L.B; ++k) {
         const TorRec tr = L.tor[k];
-        const uint4 mask = make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]);
+        // the moving side without its axis atom b, which a turn leaves where it is (as in the sweeps)
+        const uint4 mask = mask_without(make_uint4(tr.mask[0], tr.mask[1], tr.mask[2], tr.mask[3]), tr.b);
         float xax, xay, xaz, ux, uy, uz;
         axis(tr, cx, cy, cz, xax, xay, xaz, ux, uy, uz);
         float sb, cb;
