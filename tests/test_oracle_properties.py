@@ -87,6 +87,32 @@ def test_torsion_moves_are_rigid_within_fragments(tree, steps_seed, start):
 
 
 @SETTINGS
+@given(tree=trees(), step=st.integers(1, 11), start=st.integers(0, 3), pick=st.integers(0, 15))
+def test_a_turn_moves_only_its_moving_side_and_not_its_axis_atoms(tree, step, start, pick):
+    # the moving side of torsion a-b holds b, which lies on the axis: a turn leaves a, b and the fixed
+    # side where they are, and every moving atom at its distance from a and from b
+    xyz, types, bonds, rot = tree
+    ligs = I.from_parts([tree], 4)
+    tp = oracle.topology(ligs, 0)
+    if tp["B"] == 0:
+        return
+    k = pick % tp["B"]
+    srch = I.make_search(2, 2, 12, 2.0, np.zeros(3))
+    steps = np.zeros(16, np.int64)
+    steps[k] = step
+    X0 = oracle.pose_coords(ligs, srch, 0, start, np.zeros(16, np.int64))
+    X = oracle.pose_coords(ligs, srch, 0, start, steps)
+    a, b, mv = tp["tor_a"][k], tp["tor_b"][k], tp["moving"][k]
+    assert mv[b] and not mv[a]
+    still = ~mv
+    still[b] = True
+    assert np.max(np.abs(X[still] - X0[still])) < 1e-9
+    for end in (a, b):
+        assert np.allclose(np.linalg.norm(X[mv] - X[end], axis=1), np.linalg.norm(X0[mv] - X0[end], axis=1),
+                           atol=1e-9)
+
+
+@SETTINGS
 @given(tree=trees(max_n=14))
 def test_greedy_never_raises_a_start_score(field, tree):
     pocket, G = field
