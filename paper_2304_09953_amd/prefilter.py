@@ -18,7 +18,8 @@ a named unit (the test hook of that path).
 
 Every computational step of a network runs in the library's kernels, the members' mean included;
 this module orders the calls, moves ligand chunks between host and device, and does the host-side
-bookkeeping (validation error, ranks and recall).
+bookkeeping (validation error, ranks and recall).  The one model fitted on the host is the linear
+baseline of the ablation (fit_linear): a comparison for the network, never a selection of the workflow.
 """
 from __future__ import annotations
 
@@ -115,6 +116,7 @@ class Surrogate:
     metrics: dict = field(default_factory=dict)
     holdout_pred: np.ndarray | None = None  # predicted and docked best scores of the held-out ligands
     holdout_true: np.ndarray | None = None
+    holdout_linear: np.ndarray | None = None  # the linear baseline's predictions of the same ligands
 
     def predict_z(self, xb: torch.Tensor) -> np.ndarray:
         """Mean of the members' outputs (z-scores of the best docking score) for BF16 features, taken
@@ -161,16 +163,38 @@ class Surrogate:
         return np.where(lib_dev.status.cpu().numpy() == 0, z, np.float32(np.inf))
 
 
+def fit_linear(F: np.ndarray, y: np.ndarray, ridge: float = 1.0):
+    """Least squares of y on the features with an intercept, the features standardised on F (columns
+    with no spread are left out), a ridge penalty on the weights only: the linear model of the
+    pre-filter's ablation, on the same features and training ligands as the network.  Host FP64.
+    Returns the predictor X -> y."""
+    F = np.asarray(F, np.float64)
+    mu, sd = F.mean(axis=0), F.std(axis=0)
+    use = sd > 0
+    Z = (F[:, use] - mu[use]) / sd[use]
+    y = np.asarray(y, np.float64)
+    y_mean = float(y.mean())  # the intercept: every column of Z sums to zero
+    w = np.linalg.solve(Z.T @ Z + ridge * np.eye(Z.shape[1]), Z.T @ (y - y_mean))
+
+    def predict(X):
+        X = np.asarray(X, np.float64)
+        return ((X[:, use] - mu[use]) / sd[use]) @ w + y_mean
+    return predict
+
+
 def train_surrogate(pocket_dev, search_dev, train_ligs, labels: np.ndarray | None = None, n_holdout: int = 40_000,
                     n_val: int | None = None, members: int = 4, max_epochs: int = 20, batch: int = 1024,
-                    lr: float = 1e-3, seed: int = 0, log=None, checkpoint_dir: str | None = None) -> Surrogate:
+                    lr: float = 1e-3, seed: int = 0, log=None, checkpoint_dir: str | None = None,
+                    linear_baseline: bool = False) -> Surrogate:
     """Labels the training library by docking (unless given) and splits it, in order, into training,
     validation (n_val, default n_holdout / 2) and held-out (n_holdout) ligands.  Feature statistics
     come from the training part.  Each of `members` networks (its own seed for the initial weights
     and the sample order) trains for up to max_epochs and keeps the weights of the epoch with the
     lowest validation error (early stopping); the prediction is the members' mean.  Reports
     held-out R^2 and Spearman.  The generated libraries hold valid ligands only.  With
-    checkpoint_dir, every finished epoch is kept there and a rerun resumes after the last one."""
+    checkpoint_dir, every finished epoch is kept there and a rerun resumes after the last one.  With
+    linear_baseline, fit_linear on the training part's features predicts the held-out ligands too
+    (holdout_linear, and its R^2 and Spearman in the metrics)."""
     n_val = n_holdout // 2 if n_val is None else n_val
     t0 = time.perf_counter()
     if labels is None:
@@ -183,6 +207,7 @@ def train_surrogate(pocket_dev, search_dev, train_ligs, labels: np.ndarray | Non
     F, _ = SG.features(lib, bf16=False)
     mean, istd = SG.feature_stats(F[:n_tr])
     _, Xb = SG.features(lib, mean, istd, f32=False, bf16=True)
+    F_host = F.cpu().numpy() if linear_baseline and n_holdout else None
     del F
     y = labels.astype(np.float64)
     y_mean, y_std = float(y[:n_tr].mean()), float(y[:n_tr].std())
@@ -241,6 +266,13 @@ def train_surrogate(pocket_dev, search_dev, train_ligs, labels: np.ndarray | Non
         metrics["holdout_r2"] = float(1 - np.sum((pred - yh) ** 2) / np.sum((yh - yh.mean()) ** 2))
         metrics["holdout_spearman"] = float(spearmanr(pred, yh).statistic)
         s.holdout_pred, s.holdout_true = pred, yh
+        if F_host is not None:
+            t2 = time.perf_counter()
+            lin = fit_linear(F_host[:n_tr], y[:n_tr])(F_host[n_tr + n_val:])
+            metrics["linear_fit_seconds"] = time.perf_counter() - t2
+            metrics["linear_holdout_r2"] = float(1 - np.sum((lin - yh) ** 2) / np.sum((yh - yh.mean()) ** 2))
+            metrics["linear_holdout_spearman"] = float(spearmanr(lin, yh).statistic)
+            s.holdout_linear = lin
     s.metrics = metrics
     return s
 

@@ -24,7 +24,8 @@ def trained():
     dp, ds = P.DevicePocket(W.pockets[0]), P.DeviceSearch(W.search)
     ligs = I.make_ligands(6000, W.dist, W.n_types, stream="test")
     say("dock 6000 training ligands (full search), train a 2-member ensemble")
-    sur = PF.train_surrogate(dp, ds, ligs, n_holdout=1500, n_val=500, members=2, max_epochs=10, batch=256)
+    sur = PF.train_surrogate(dp, ds, ligs, n_holdout=1500, n_val=500, members=2, max_epochs=10, batch=256,
+                             linear_baseline=True)
     say(f"surrogate metrics {sur.metrics}")
     return P, PF, W, dp, ds, ligs, sur
 
@@ -37,7 +38,10 @@ def test_network_beats_selection_without_it(trained):
     net = PF.recall_curve(PF.ranks(pred), true, fr, len(true), top=0.05)
     big = PF.recall_curve(PF.ranks(-ligs.n_atoms[ho].astype(np.float64)), true, fr, len(true), top=0.05)
     small = PF.recall_curve(PF.ranks(ligs.n_atoms[ho].astype(np.float64)), true, fr, len(true), top=0.05)
-    say(f"recall of the true top 5 %: network {net}, largest first {big}, smallest first {small}, random = f")
+    lin = PF.recall_curve(PF.ranks(sur.holdout_linear), true, fr, len(true), top=0.05)
+    say(f"recall of the true top 5 %: network {net}, linear model of the same features {lin} (held-out R^2 "
+        f"{sur.metrics['linear_holdout_r2']:.3f}), largest first {big}, smallest first {small}, random = f")
+    assert sur.holdout_linear.shape == true.shape and np.isfinite(sur.metrics["linear_holdout_r2"])
     assert sur.metrics["holdout_spearman"] > 0.8
     for f in fr:
         assert net[f] >= f + 0.4                       # random selection keeps a share f

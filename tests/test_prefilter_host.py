@@ -67,6 +67,28 @@ def test_cascade_recall_and_its_calibration():
     assert PF.calibrate_cascade(-true, -true, true, 0.03, 0.5) == 1.0
 
 
+def test_linear_baseline_fits_a_linear_target_and_shrinks_with_the_ridge():
+    rng = np.random.default_rng(3)
+    F = rng.normal(size=(3000, 40)) * rng.uniform(0.1, 5.0, 40) + rng.normal(size=40)
+    F[:, 7] = 2.5  # a constant column carries no information and must not break the fit
+    w = rng.normal(size=40)
+    y = F @ w + 3.0
+    X = rng.normal(size=(500, 40)) * 2.0
+    X[:, 7] = 2.5
+    # an exact linear target is reproduced away from the training points, intercept included
+    got = PF.fit_linear(F, y, ridge=1e-9)(X)
+    assert np.allclose(got, X @ w + 3.0, rtol=0, atol=1e-6 * np.abs(X @ w + 3.0).max())
+    # the ridge shrinks the weights towards the mean label; noise does not move the intercept
+    assert np.allclose(PF.fit_linear(F, y, ridge=1e12)(X), y.mean(), atol=1e-3 * np.abs(y).max())
+    noisy = y + rng.normal(scale=0.1, size=len(y))
+    fit = PF.fit_linear(F, noisy, ridge=1.0)
+    assert abs(np.mean(fit(F)) - noisy.mean()) < 1e-9 * np.abs(noisy).max()
+    # with no penalty it is the least-squares fit: the residual is orthogonal to every feature
+    r = noisy - PF.fit_linear(F, noisy, ridge=1e-9)(F)
+    Fc = F - F.mean(0)
+    assert np.all(np.abs(Fc.T @ r) <= 1e-8 * np.linalg.norm(Fc, axis=0) * np.linalg.norm(r) + 1e-12)
+
+
 def test_checkpoint_round_trip_and_manifest(tmp_path):
     d = str(tmp_path / "ck")
     params = {"kind": "screen", "n_lib": 10, "frac": 0.25, "search": {"n_steps": 8, "starts": "ab"}}
