@@ -447,18 +447,21 @@ def test_pocket96_lib100k_sample_full_search(P):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("pi,pick", [(3, "heavy"), (1, "mixed")])
+@pytest.mark.parametrize("pi,pick", [(3, "heavy"), (1, "mixed"), (0, "mixed"), (2, "heavy")])
 def test_pockets4_pockets_against_the_oracle(P, pi, pick):
-    """Pockets of the 250k-ligand workload against the oracle on their own grids, full 8192-start
-    search: the largest (128^3 x 16 types) with two heavy-tail ligands (80-120 atoms), and the 80^3
-    pocket with one heavy-tail and two typical ligands."""
+    """Every pocket of the 250k-ligand workload against the oracle on its own grids, full 8192-start
+    search: the 128^3 and 96^3 pockets (x 16 types) with two heavy-tail ligands (80-120 atoms) each,
+    the 80^3 and 64^3 pockets with one heavy-tail and two typical ligands each."""
     W = I.workload("pockets4-lib250k")
     pocket = W.pockets[pi]
-    assert pocket.dims == ((128, 128, 128) if pi == 3 else (80, 80, 80))
+    assert pocket.dims == ((64, 64, 64), (80, 80, 80), (96, 96, 96), (128, 128, 128))[pi]
     lib_all = W.ligands(n_lig=2000)
     heavy = np.flatnonzero((lib_all.n_atoms >= 80) & (lib_all.n_rot >= 4))
     typical = np.flatnonzero((np.abs(lib_all.n_atoms - 35) <= 3) & (lib_all.n_rot == 5))
-    sel = heavy[:2] if pick == "heavy" else np.sort(np.r_[heavy[2:3], typical[:2]])
+    # ligands of their own per pocket: heavy-tail ones 0-1 and 3-4 alone, 2 and 5 beside two typical ones
+    h0, t0 = {3: (0, 0), 1: (2, 0), 2: (3, 0), 0: (5, 2)}[pi]
+    sel = heavy[h0:h0 + 2] if pick == "heavy" else np.sort(np.r_[heavy[h0:h0 + 1], typical[t0:t0 + 2]])
+    assert len(sel) == (2 if pick == "heavy" else 3)
     ligs = lib_all.subset(sel)
     say(f"pockets4 {pocket.dims[0]}^3 pocket, ligands {sel.tolist()} (n {ligs.n_atoms.tolist()}, "
         f"B {ligs.n_rot.tolist()}), full search")
