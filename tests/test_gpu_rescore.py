@@ -15,30 +15,12 @@ def say(msg):
     print(f"[gpu-case] {msg}", flush=True)
 
 
-@pytest.fixture(scope="module")
-def env():
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
+def _check_against_oracle(pocket, ligs, srch, fin, res, n_keep, rmsd_min):
+    """Every ligand's picks, replayed poses, FP64 rescores, filter decisions and best pose against the
+    oracle; returns the number of ligands whose filter decisions differ at an RMSD within 1e-4 of the
+    threshold (FP32 poses)."""
     from paper_2304_09953_amd import pipeline as P
-    W = I.workload("pocket48-lib100")
-    pocket = W.pockets[0]
-    ligs = W.ligands().subset(np.arange(0, 100, 5))
-    return P, W, pocket, ligs, P.DevicePocket(pocket), P.DeviceLibrary(ligs)
-
-
-@pytest.mark.parametrize("n_keep,rmsd_min,top,passes,restarts",
-                         [(8, 1.0, 0, 1, 0), (16, 2.5, 40, 2, 0), (3, 0.0, 0, 1, 0), (8, 1.0, 0, 1, 2)])
-def test_rescore_matches_oracle(env, n_keep, rmsd_min, top, passes, restarts):
-    P, W, pocket, ligs, dp, lib = env
-    srch = dataclasses.replace(W.search, sweep_top=top, passes=passes, restarts=restarts,
-                               init_steps=I.restart_steps(restarts, W.search.n_steps) if restarts else None)
-    ds = P.DeviceSearch(srch)
-    QT, n = srch.n_searched, ligs.n_lig  # searched starts: with restarts, (1 + R) rigid-start sets
-    say(f"rescore: keep {n_keep}, rmsd_min {rmsd_min}, sweep_top {top}, passes {passes}, restarts {restarts}")
-    scr = P.screen(dp, lib, ds, start_scores=True)
-    res = P.rescore(dp, lib, ds, scr.start_scores.view(n, QT), n_keep, rmsd_min, want_xyz=True)
-    torch.cuda.synchronize()
-    fin = scr.start_scores.view(n, QT).cpu().numpy()
+    n, QT = fin.shape
     start = res.pose_start.cpu().numpy()
     steps = P.steps_numpy(res.pose_steps.view(-1)).reshape(n, n_keep, -1)
     score = res.pose_score.cpu().numpy()
@@ -77,7 +59,66 @@ def test_rescore_matches_oracle(env, n_keep, rmsd_min, top, passes, restarts):
             assert best_pose[l] == -1 and np.isinf(best[l])
         if rmsd_min == 0.0:
             assert np.array_equal(kept, live)
+    return flips
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_09953_amd import pipeline as P
+    W = I.workload("pocket48-lib100")
+    pocket = W.pockets[0]
+    ligs = W.ligands().subset(np.arange(0, 100, 5))
+    return P, W, pocket, ligs, P.DevicePocket(pocket), P.DeviceLibrary(ligs)
+
+
+@pytest.mark.parametrize("n_keep,rmsd_min,top,passes,restarts",
+                         [(8, 1.0, 0, 1, 0), (16, 2.5, 40, 2, 0), (3, 0.0, 0, 1, 0), (8, 1.0, 0, 1, 2)])
+def test_rescore_matches_oracle(env, n_keep, rmsd_min, top, passes, restarts):
+    P, W, pocket, ligs, dp, lib = env
+    srch = dataclasses.replace(W.search, sweep_top=top, passes=passes, restarts=restarts,
+                               init_steps=I.restart_steps(restarts, W.search.n_steps) if restarts else None)
+    ds = P.DeviceSearch(srch)
+    QT, n = srch.n_searched, ligs.n_lig  # searched starts: with restarts, (1 + R) rigid-start sets
+    say(f"rescore: keep {n_keep}, rmsd_min {rmsd_min}, sweep_top {top}, passes {passes}, restarts {restarts}")
+    scr = P.screen(dp, lib, ds, start_scores=True)
+    res = P.rescore(dp, lib, ds, scr.start_scores.view(n, QT), n_keep, rmsd_min, want_xyz=True)
+    torch.cuda.synchronize()
+    fin = scr.start_scores.view(n, QT).cpu().numpy()
+    flips = _check_against_oracle(pocket, ligs, srch, fin, res, n_keep, rmsd_min)
     say(f"threshold flips: {flips}")
+    assert flips <= 1
+
+
+@pytest.mark.timeout(600)
+def test_rescore_at_full_size():
+    """The benchmark's pocket and search (96^3 x 16 types, 256 quaternions x 32 translations, S = 256) on
+    a stratified handful of its library: the largest and the smallest ligand, one with 12 torsions, one
+    with none, and four seeded draws; 8 poses kept per ligand, 1 A apart."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_09953_amd import pipeline as P
+    W = I.workload("pocket96-lib100k")
+    pocket = W.pockets[0]
+    lib_all = W.ligands(n_lig=3000)
+    n_rot = lib_all.n_rot
+    pick = [int(np.argmax(lib_all.n_atoms)), int(np.argmin(lib_all.n_atoms)), int(np.flatnonzero(n_rot == 12)[0]),
+            int(np.flatnonzero(n_rot == 0)[0])]
+    rest = np.setdiff1d(np.arange(lib_all.n_lig), pick)
+    pick += np.random.default_rng(3).choice(rest, 4, replace=False).tolist()
+    sel = np.sort(np.unique(pick))
+    ligs = lib_all.subset(sel)
+    say(f"rescore at full size: ligands {sel.tolist()} (n {ligs.n_atoms.tolist()}, B {ligs.n_rot.tolist()}), "
+        "keep 8, rmsd_min 1.0")
+    dp, lib, ds = P.DevicePocket(pocket), P.DeviceLibrary(ligs), P.DeviceSearch(W.search)
+    n, QT = ligs.n_lig, W.search.n_searched
+    scr = P.screen(dp, lib, ds, start_scores=True)
+    res = P.rescore(dp, lib, ds, scr.start_scores.view(n, QT), 8, 1.0, want_xyz=True)
+    torch.cuda.synchronize()
+    fin = scr.start_scores.view(n, QT).cpu().numpy()
+    flips = _check_against_oracle(pocket, ligs, W.search, fin, res, 8, 1.0)
+    say(f"full size: threshold flips {flips}, kept poses {np.isfinite(res.pose_rescore.cpu().numpy()).sum(1).tolist()}")
     assert flips <= 1
 
 
