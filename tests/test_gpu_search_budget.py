@@ -108,6 +108,38 @@ def test_restarts_match_oracle(env, restarts, passes):
     assert g["poses"] == int(np.sum(N * (1 + passes * B * (srch.n_steps - 1))))
 
 
+@pytest.mark.timeout(600)
+def test_restarts_and_passes_at_full_size():
+    """The benchmark's pocket and search (96^3 x 16 types, 256 x 32 rigid starts, S = 256) with one torsion
+    restart of every rigid start and two greedy passes (16384 searched starts per ligand), on two of its
+    ligands of median size, against the oracle start by start."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_09953_amd import pipeline as P
+    W = I.workload("pocket96-lib100k")
+    pocket = W.pockets[0]
+    lib_all = W.ligands(n_lig=400)
+    med = np.flatnonzero((np.abs(lib_all.n_atoms - 30) <= 3) & (lib_all.n_rot >= 3) & (lib_all.n_rot <= 5))[:2]
+    ligs = lib_all.subset(med)
+    srch = dataclasses.replace(W.search, passes=2, restarts=1, init_steps=I.restart_steps(1, W.search.n_steps))
+    N, QT = srch.n_searched, srch.n_starts
+    say(f"pocket96 full size, ligands {med.tolist()} (n {ligs.n_atoms.tolist()}, B {ligs.n_rot.tolist()}): "
+        f"1 restart per start, 2 passes, {N} searched starts each")
+    G = oracle.build_grids(pocket)
+    g = _screen(P, P.DevicePocket(pocket), ligs, srch)
+    orc = oracle.dock(pocket, G, ligs, srch, per_start=True)
+    assert g["finals"].shape == (ligs.n_lig, N) and np.all(np.isfinite(g["finals"]))
+    st = check_per_start(pocket, G, ligs, srch, g["finals"], g["start_steps"], orc)
+    say(f"per-start: {st}")
+    assert st["agree"] >= 0.99 * st["starts"]
+    assert np.array_equal(g["score"], g["finals"].min(1)) and np.array_equal(g["start"], np.argmin(g["finals"], 1))
+    sel = np.arange(ligs.n_lig)
+    check_exact_and_valid(pocket, G, ligs, srch, sel, g["score"], g["start"], g["steps"])
+    n_flag = check_optimal(pocket, G, ligs, srch, sel, g["score"], g["start"], orc, g["finals"], g["start_steps"])
+    say(f"{n_flag} ligands split at near-ties; best {g['score'].tolist()} vs oracle {orc['best'].tolist()}")
+    assert g["poses"] == int(np.sum(N * (1 + 2 * ligs.n_rot * (srch.n_steps - 1))))
+
+
 def test_zero_restarts_repeat_the_plain_search(env):
     P, W, pocket, G, ligs, dp = env
     say("two restarts with zero initial turns against the plain search")
