@@ -71,6 +71,17 @@ def test_features_match_oracle(env):
                                                      istd.cpu().numpy().astype(np.float64)), rtol=1e-4, atol=1e-4)
 
 
+@pytest.mark.timeout(300)
+def test_features_at_library_scale(env):
+    """The first 20000 ligands of the 100k-ligand benchmark library (the pre-filter's inputs at their
+    real distribution, 15-70 atoms): every count against the oracle."""
+    P, SG = env
+    ligs = I.workload("pocket96-lib100k").ligands(n_lig=20000)
+    say("features of the benchmark library's first 20000 ligands")
+    F, _ = SG.features(P.DeviceLibrary(ligs), bf16=False)
+    _check_counts(F.cpu().numpy(), ligs)
+
+
 def test_invalid_ligands_get_zero_features(env):
     P, SG = env
     from test_gpu_parity import _edge_library
